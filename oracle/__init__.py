@@ -1,0 +1,145 @@
+"""FP64 CPU oracle of three-filters-to-normal — TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product path (the HIP library and
+its Python binding) never loads it, and it shares no code with them.
+
+``sne_oracle.c`` holds the arithmetic (see its header for the definition it
+follows, Sec. III of the paper); this module builds it with gcc, loads it with
+ctypes and marshals numpy arrays.  ``exact.py`` is an independent brute-force
+evaluation in rational arithmetic for tiny integer images.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "sne_oracle.c")
+LIB = os.path.join(HERE, "libsne_oracle.so")
+
+KINDS = {"depth_f32": 0, "depth_u16": 1, "depth_f16": 2, "disparity_f32": 3,
+         "depth_f64": 4, "disparity_f64": 5}
+KIND_DTYPE = {"depth_f32": np.float32, "depth_u16": np.uint16, "depth_f16": np.float16,
+              "disparity_f32": np.float32, "depth_f64": np.float64,
+              "disparity_f64": np.float64}
+GRADS = {"fd": 0, "sobel": 1, "scharr": 2, "prewitt": 3}
+AGGS = {"mean": 0, "median": 1}
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain C, -O2, OpenMP, no intrinsics)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-std=c11", "-Wall", "-Wextra",
+                               "-shared", "-fPIC", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build(force=True)
+        lib = ctypes.CDLL(LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        common = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                  ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                  ctypes.c_double, ctypes.c_int, ctypes.c_int]
+        lib.orc_estimate.argtypes = common + [dp, ctypes.c_void_p, dp, ctypes.c_void_p,
+                                              ctypes.c_int]
+        lib.orc_estimate.restype = ctypes.c_int
+        lib.orc_estimate_pixels.argtypes = common + [ctypes.c_void_p, ctypes.c_int64, dp,
+                                                     ctypes.c_void_p, dp, ctypes.c_void_p,
+                                                     ctypes.c_int]
+        lib.orc_estimate_pixels.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _dp(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _prep(raw: np.ndarray, kind: str) -> np.ndarray:
+    if kind not in KINDS:
+        raise ValueError("unknown kind %r" % kind)
+    raw = np.ascontiguousarray(raw)
+    want = KIND_DTYPE[kind]
+    if raw.dtype != want:
+        raise TypeError("kind %s needs %s input, got %s" % (kind, np.dtype(want), raw.dtype))
+    if raw.ndim != 2:
+        raise ValueError("expected a 2-D image")
+    return raw
+
+
+def estimate(raw: np.ndarray, kind: str, K: Sequence[float], grad: str = "fd",
+             agg: str = "mean", tc: float = 1.0, threads: int = 0, unnorm: bool = False,
+             mcount: bool = False):
+    """Normals [3,H,W] float64 and mask [H,W] uint8 of one image.
+
+    K = (fx, fy, u0, v0) as the values the caller wants used (pass the FP32
+    values a GPU run used to compare like with like).  With ``unnorm`` the
+    unnormalised n' = (n_x, n_y, n_z) [3,H,W] is returned too; with ``mcount``
+    the number of candidates kept per pixel [H,W] (-1 masked, 0 degenerate)."""
+    raw = _prep(raw, kind)
+    H, W = raw.shape
+    fx, fy, u0, v0 = (float(x) for x in K)
+    nrm = np.zeros((3, H, W), np.float64)
+    msk = np.zeros((H, W), np.uint8)
+    un = np.zeros((3, H, W), np.float64) if unnorm else None
+    mc = np.zeros((H, W), np.int32) if mcount else None
+    rc = _load().orc_estimate(raw.ctypes.data, KINDS[kind], H, W, W, fx, fy, u0, v0, float(tc),
+                              GRADS[grad], AGGS[agg], _dp(nrm), msk.ctypes.data, _dp(un),
+                              None if mc is None else mc.ctypes.data, int(threads))
+    if rc != 0:
+        raise ValueError("oracle rejected its arguments (rc=%d)" % rc)
+    out = [nrm, msk]
+    if unnorm:
+        out.append(un)
+    if mcount:
+        out.append(mc)
+    return tuple(out)
+
+
+def estimate_pixels(raw: np.ndarray, kind: str, K: Sequence[float], pix: np.ndarray,
+                    grad: str = "fd", agg: str = "mean", tc: float = 1.0, threads: int = 0,
+                    unnorm: bool = False, mcount: bool = False):
+    """Normals [n,3] and mask [n] at flat pixel indices ``pix`` (v*W + u)."""
+    raw = _prep(raw, kind)
+    H, W = raw.shape
+    pix = np.ascontiguousarray(pix, dtype=np.int64)
+    n = pix.size
+    fx, fy, u0, v0 = (float(x) for x in K)
+    nrm = np.zeros((n, 3), np.float64)
+    msk = np.zeros(n, np.uint8)
+    un = np.zeros((n, 3), np.float64) if unnorm else None
+    mc = np.zeros(n, np.int32) if mcount else None
+    rc = _load().orc_estimate_pixels(raw.ctypes.data, KINDS[kind], H, W, W, fx, fy, u0, v0,
+                                     float(tc), GRADS[grad], AGGS[agg], pix.ctypes.data, n,
+                                     _dp(nrm), msk.ctypes.data, _dp(un),
+                                     None if mc is None else mc.ctypes.data, int(threads))
+    if rc != 0:
+        raise ValueError("oracle rejected its arguments (rc=%d)" % rc)
+    out = [nrm, msk]
+    if unnorm:
+        out.append(un)
+    if mcount:
+        out.append(mc)
+    return tuple(out)
+
+
+def angular_error_deg(a: np.ndarray, b: np.ndarray, axis: int = 0) -> np.ndarray:
+    """Angle between vectors a and b (FP64) as atan2(|a x b|, a.b) in degrees:
+    the psi of Sec. IV-A, well conditioned near 0."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    cr = np.cross(a, b, axisa=axis, axisb=axis, axisc=axis)
+    return np.degrees(np.arctan2(np.linalg.norm(cr, axis=axis), np.sum(a * b, axis=axis)))

@@ -1,0 +1,300 @@
+/*
+ * sne_oracle.c - plain FP64 CPU reference of three-filters-to-normal (3F2N).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle the HIP path is checked
+ * against; it shares no code, header, table or helper with the HIP library,
+ * and the product path never loads it.  It is slow on purpose: every pixel is
+ * evaluated on its own, in double precision, in the order the method is
+ * stated.
+ *
+ * What is computed, per pixel p = (v, u) (v = row, u = column, pixel centres
+ * at integer coordinates), following Sec. III of the paper:
+ *
+ *   1. Validity: a raw sample is valid iff it is finite and > 0.  The output
+ *      mask is 1 iff p is an interior pixel (1 <= u <= W-2, 1 <= v <= H-2) and
+ *      all 9 samples of its 3x3 window are valid; otherwise the normal is
+ *      (+0, +0, +0) and the mask 0.  (The paper does not treat holes or the
+ *      border; this strict reading keeps the mask a function of raw
+ *      predicates only.)
+ *   2. Degenerate window: if the raw value of p equals that of all 8
+ *      neighbours the normal is (0, 0, -1) (Sec. III, the remark after
+ *      eq. nx2_ny2_nz2).
+ *   3. Depth z of each window sample: the raw value for depth kinds; for a
+ *      disparity image z = f t_c / d with f = fx = fy (eq. z_d).
+ *   4. The filtered image s: inverse depth 1/z for depth kinds (the image
+ *      "storing the values of 1/z" of Sec. III), the raw disparity d for the
+ *      disparity kind (eq. nx2_ny2_nz3).
+ *   5. Filters 1 and 2: G_u = K_x (*) s and G_v = K_y (*) s over the 3x3
+ *      window (correlation, so G_u approximates +ds/du), K_y = K_x^T, with the
+ *      unnormalised kernels FD, Sobel, Scharr and Prewitt (Sec. IV-B).  Each
+ *      kernel is antisymmetric, so the nine taps are summed line by line (a
+ *      row of K_x, a column of K_y): a window that is mirror-symmetric about
+ *      its centre line then gives exactly zero.
+ *   6. n_x = fx G_u, n_y = fy G_v for depth (eq. nx2_ny2_nz2);
+ *      n_x = G_u,  n_y = G_v    for disparity (eq. nx2_ny2_nz3).
+ *   7. Back-projection P(q) = z(q) ((u_q - u0)/fx, (v_q - v0)/fy, 1)
+ *      (eq. intrinisc_matrix) and, for every neighbour q_j whose raw value
+ *      differs from that of p, the candidate
+ *        c_j = (dX_j n_x + dY_j n_y) / dZ_j,  (dX, dY, dZ) = P(q_j) - P(p)
+ *      (eq. nz1 after the common factor -b is divided out, eq. nx2_ny2_nz2).
+ *      Neighbours with an equal raw value (dZ = 0) are left out; m is the
+ *      number of candidates kept.
+ *   8. Filter 3, Phi: the arithmetic mean of the m candidates, or their
+ *      median (sorted ascending; odd m: the middle one, even m: the mean of
+ *      the two middle ones).
+ *   9. n_z = -Phi (eq. nx2_ny2_nz2).
+ *  10. The vector n' = (n_x, n_y, n_z) equals -n/b for a plane n.p + b = 0,
+ *      i.e. it points away from the camera (n'.p = 1 on the plane up to the
+ *      kernel's scale).  The output is the camera-facing unit normal
+ *      -n'/|n'|, which is continuous with the (0, 0, -1) of the degenerate
+ *      case; |n'| = 0 also yields (0, 0, -1).
+ *
+ * Raw kinds: FP32 depth, uint16 depth (any unit, read as an integer), FP16
+ * depth, FP32 disparity, and - for the exactness tests only - FP64 depth and
+ * FP64 disparity.
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_OK 0
+#define ORC_EARG -1
+
+enum { K_DEPTH_F32 = 0, K_DEPTH_U16 = 1, K_DEPTH_F16 = 2, K_DISP_F32 = 3,
+       K_DEPTH_F64 = 4, K_DISP_F64 = 5 };
+enum { G_FD = 0, G_SOBEL = 1, G_SCHARR = 2, G_PREWITT = 3 };
+enum { A_MEAN = 0, A_MEDIAN = 1 };
+
+/* Horizontal-derivative kernels K_x[row][col]; row/col index = offset + 1. */
+static const double KX[4][3][3] = {
+    {{0, 0, 0}, {-1, 0, 1}, {0, 0, 0}},        /* FD [-1 0 1]   */
+    {{-1, 0, 1}, {-2, 0, 2}, {-1, 0, 1}},      /* Sobel         */
+    {{-3, 0, 3}, {-10, 0, 10}, {-3, 0, 3}},    /* Scharr        */
+    {{-1, 0, 1}, {-1, 0, 1}, {-1, 0, 1}},      /* Prewitt       */
+};
+
+typedef struct {
+    const void *raw;
+    int kind, H, W;
+    int64_t pitch;               /* elements between rows */
+    double fx, fy, u0, v0, tc;
+    int grad, agg;
+} orc_img;
+
+/* IEEE binary16 -> double, from the format's definition. */
+static double half_bits_to_double(uint16_t h) {
+    int sign = (h >> 15) & 1, e = (h >> 10) & 0x1f, f = h & 0x3ff;
+    double mag;
+    if (e == 0)
+        mag = ldexp((double)f, -24);                 /* subnormal */
+    else if (e == 31)
+        mag = f ? NAN : INFINITY;
+    else
+        mag = ldexp((double)(1024 + f), e - 25);     /* (1 + f/1024) 2^(e-15) */
+    return sign ? -mag : mag;
+}
+
+static double raw_at(const orc_img *im, int v, int u) {
+    int64_t off = (int64_t)v * im->pitch + u;
+    switch (im->kind) {
+    case K_DEPTH_F32:
+    case K_DISP_F32: return (double)((const float *)im->raw)[off];
+    case K_DEPTH_U16: return (double)((const uint16_t *)im->raw)[off];
+    case K_DEPTH_F16: return half_bits_to_double(((const uint16_t *)im->raw)[off]);
+    default: return ((const double *)im->raw)[off];
+    }
+}
+
+static int is_disparity(int kind) { return kind == K_DISP_F32 || kind == K_DISP_F64; }
+
+static int cmp_double(const void *a, const void *b) {
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+/* One pixel.  out[3]: unit normal; unnorm[3] (may be NULL): n' = (n_x, n_y,
+ * n_z) before the final orientation and normalisation; *mask; *m_out: number
+ * of candidates kept (-1 when masked, 0 when degenerate). */
+static void pixel(const orc_img *im, int v, int u, double out[3], unsigned char *mask,
+                  double unnorm[3], int *m_out) {
+    out[0] = out[1] = out[2] = 0.0;
+    if (unnorm) unnorm[0] = unnorm[1] = unnorm[2] = 0.0;
+    *mask = 0;
+    *m_out = -1;
+    if (u < 1 || u > im->W - 2 || v < 1 || v > im->H - 2) return;
+
+    double raw[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            raw[a][b] = raw_at(im, v + a - 1, u + b - 1);
+            if (!(isfinite(raw[a][b]) && raw[a][b] > 0.0)) return;
+        }
+    *mask = 1;
+
+    int all_equal = 1;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            if (raw[a][b] != raw[1][1]) all_equal = 0;
+    if (all_equal) {
+        out[2] = -1.0;
+        *m_out = 0;
+        return;
+    }
+
+    const int disp = is_disparity(im->kind);
+    double z[3][3], s[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            z[a][b] = disp ? im->fx * im->tc / raw[a][b] : raw[a][b];
+            s[a][b] = disp ? raw[a][b] : 1.0 / z[a][b];
+        }
+
+    /* Filters 1 and 2: correlation with K_x and K_y = K_x^T, line by line. */
+    const double (*K)[3] = KX[im->grad];
+    double Gu = 0.0, Gv = 0.0;
+    for (int a = 0; a < 3; ++a) {          /* rows of K_x */
+        double line = 0.0;
+        for (int b = 0; b < 3; ++b) line += K[a][b] * s[a][b];
+        Gu += line;
+    }
+    for (int b = 0; b < 3; ++b) {          /* columns of K_y: K_y[a][b] = K_x[b][a] */
+        double line = 0.0;
+        for (int a = 0; a < 3; ++a) line += K[b][a] * s[a][b];
+        Gv += line;
+    }
+    const double nx = disp ? Gu : im->fx * Gu;
+    const double ny = disp ? Gv : im->fy * Gv;
+
+    /* Back-projected window points. */
+    double P[3][3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            const double uq = (double)(u + b - 1), vq = (double)(v + a - 1);
+            P[a][b][0] = z[a][b] * (uq - im->u0) / im->fx;
+            P[a][b][1] = z[a][b] * (vq - im->v0) / im->fy;
+            P[a][b][2] = z[a][b];
+        }
+
+    double c[8];
+    int m = 0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            if (a == 1 && b == 1) continue;
+            if (raw[a][b] == raw[1][1]) continue;     /* dZ = 0: left out */
+            const double dX = P[a][b][0] - P[1][1][0];
+            const double dY = P[a][b][1] - P[1][1][1];
+            const double dZ = P[a][b][2] - P[1][1][2];
+            c[m++] = (dX * nx + dY * ny) / dZ;
+        }
+    *m_out = m;
+
+    double phi;
+    if (im->agg == A_MEAN) {
+        double sum = 0.0;
+        for (int j = 0; j < m; ++j) sum += c[j];
+        phi = sum / m;
+    } else {
+        qsort(c, (size_t)m, sizeof(double), cmp_double);
+        phi = (m % 2) ? c[m / 2] : 0.5 * (c[m / 2 - 1] + c[m / 2]);
+    }
+    const double nz = -phi;
+
+    if (unnorm) {
+        unnorm[0] = nx;
+        unnorm[1] = ny;
+        unnorm[2] = nz;
+    }
+    const double norm = sqrt(nx * nx + ny * ny + nz * nz);
+    if (norm == 0.0) {
+        out[2] = -1.0;
+        return;
+    }
+    out[0] = -nx / norm;
+    out[1] = -ny / norm;
+    out[2] = -nz / norm;
+}
+
+static int check_args(const void *raw, int kind, int H, int W, int64_t pitch, double fx,
+                      double fy, int grad, int agg) {
+    if (!raw || H < 1 || W < 1 || pitch < W) return ORC_EARG;
+    if (kind < K_DEPTH_F32 || kind > K_DISP_F64) return ORC_EARG;
+    if (grad < G_FD || grad > G_PREWITT || agg < A_MEAN || agg > A_MEDIAN) return ORC_EARG;
+    if (!(fx > 0.0) || !(fy > 0.0)) return ORC_EARG;
+    if (is_disparity(kind) && fx != fy) return ORC_EARG;
+    return ORC_OK;
+}
+
+/* Whole image.  normals: [3][H][W] doubles (planar); mask: [H][W];
+ * unnorm: optional [3][H][W]; mcount: optional [H][W] int (candidates kept,
+ * -1 masked).  nthreads <= 0 uses the OpenMP default. */
+int orc_estimate(const void *raw, int kind, int H, int W, int64_t pitch, double fx, double fy,
+                 double u0, double v0, double tc, int grad, int agg, double *normals,
+                 unsigned char *mask, double *unnorm, int *mcount, int nthreads) {
+    if (check_args(raw, kind, H, W, pitch, fx, fy, grad, agg) != ORC_OK || !normals || !mask)
+        return ORC_EARG;
+    orc_img im = {raw, kind, H, W, pitch, fx, fy, u0, v0, tc, grad, agg};
+    const int64_t plane = (int64_t)H * W;
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads)
+#endif
+    for (int v = 0; v < H; ++v)
+        for (int u = 0; u < W; ++u) {
+            double n[3], un[3];
+            unsigned char mk;
+            int m;
+            pixel(&im, v, u, n, &mk, un, &m);
+            const int64_t i = (int64_t)v * W + u;
+            normals[i] = n[0];
+            normals[plane + i] = n[1];
+            normals[2 * plane + i] = n[2];
+            mask[i] = mk;
+            if (unnorm) {
+                unnorm[i] = un[0];
+                unnorm[plane + i] = un[1];
+                unnorm[2 * plane + i] = un[2];
+            }
+            if (mcount) mcount[i] = m;
+        }
+    return ORC_OK;
+}
+
+/* Selected pixels only (flat indices v*W + u).  normals: [n][3]; mask: [n];
+ * unnorm optional [n][3]; mcount optional [n]. */
+int orc_estimate_pixels(const void *raw, int kind, int H, int W, int64_t pitch, double fx,
+                        double fy, double u0, double v0, double tc, int grad, int agg,
+                        const int64_t *pix, int64_t n, double *normals, unsigned char *mask,
+                        double *unnorm, int *mcount, int nthreads) {
+    if (check_args(raw, kind, H, W, pitch, fx, fy, grad, agg) != ORC_OK || !pix || !normals ||
+        !mask || n < 0)
+        return ORC_EARG;
+    for (int64_t k = 0; k < n; ++k)
+        if (pix[k] < 0 || pix[k] >= (int64_t)H * W) return ORC_EARG;
+    orc_img im = {raw, kind, H, W, pitch, fx, fy, u0, v0, tc, grad, agg};
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+#endif
+    for (int64_t k = 0; k < n; ++k) {
+        double nn[3], un[3];
+        unsigned char mk;
+        int m;
+        pixel(&im, (int)(pix[k] / W), (int)(pix[k] % W), nn, &mk, un, &m);
+        normals[3 * k] = nn[0];
+        normals[3 * k + 1] = nn[1];
+        normals[3 * k + 2] = nn[2];
+        mask[k] = mk;
+        if (unnorm) {
+            unnorm[3 * k] = un[0];
+            unnorm[3 * k + 1] = un[1];
+            unnorm[3 * k + 2] = un[2];
+        }
+        if (mcount) mcount[k] = m;
+    }
+    return ORC_OK;
+}
