@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Benchmark of the three-filters-to-normal hot path on one MI355X.
+
+Step = one launch of the fused stencil over a batch of 64 synthetic 480x640
+FP32 depth frames (0.5 % depth noise, 3 % holes), Sobel gradients, median
+aggregation, FP32 normals plus the validity mask: every step of the method in
+one kernel.  Four such batches (1.34 GB of inputs and outputs) are rotated so
+that the 256 MB last-level cache cannot hold a batch between its uses.
+
+Prints one JSON line.  `roofline.achieved` is the algorithmic bytes of one
+launch (4 B depth in + 12 B normals out + 1 B mask out per pixel) over the
+kernel's mean duration, timed with HIP events on the launch stream.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2005_08165_amd", "csrc", "sne_kernels.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source."""
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+        e = d.get(workload)
+        if e and e.get("kernel_sha") == kernel_hash():
+            return e.get("bytes_per_launch")
+    except (OSError, ValueError):
+        pass
+    return None
+
+
+def make_batch(torch, S, cam, seeds, device):
+    return torch.stack([S.make_cluttered(s, cam, device=device).raw for s in seeds])
+
+
+def time_launches(torch, fn, warmup, steps):
+    """Wall time and event time of `steps` back-to-back calls of fn(i)."""
+    st = torch.cuda.current_stream()
+    for i in range(warmup):
+        fn(i)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(st)
+    for i in range(steps):
+        fn(warmup + i)
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, e0.elapsed_time(e1) / 1e3
+
+
+def plain_single_frame(torch, S, sne, grad, agg, reps=200):
+    """One 480x640 frame per launch: mean and p50/p99 of launch-to-completion
+    latency over `reps` synchronous calls, and the back-to-back rate."""
+    fr = S.make_indoor(0, device="cuda")
+    raw = fr.raw
+    K = fr.cam.as_tuple()
+    nrm = torch.empty((3, 480, 640), device="cuda")
+    msk = torch.empty((480, 640), dtype=torch.uint8, device="cuda")
+    for _ in range(20):
+        sne.estimate(raw, K, "depth_f32", grad, agg, normals=nrm, mask=msk)
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        sne.estimate(raw, K, "depth_f32", grad, agg, normals=nrm, mask=msk)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    lat.sort()
+    wall, ev = time_launches(torch, lambda i: sne.estimate(raw, K, "depth_f32", grad, agg,
+                                                           normals=nrm, mask=msk), 20, reps)
+    px = 480 * 640
+    return {"variant": "%s-%s" % (grad, agg), "mpix_per_s": round(px * reps / ev / 1e6, 1),
+            "frames_per_s": round(reps / ev, 1),
+            "us_per_frame_back_to_back": round(ev / reps * 1e6, 2),
+            "latency_us_p50": round(lat[len(lat) // 2] * 1e6, 1),
+            "latency_us_p99": round(lat[int(len(lat) * 0.99) - 1] * 1e6, 1)}
+
+
+def cpu_baseline(host_batch, K, grad, agg, budget_s=20.0):
+    """The FP64 oracle, as it stands, on the host's cores over a bounded
+    sample of the same workload."""
+    import numpy as np
+    import oracle
+    threads = os.cpu_count() or 1
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    K32 = tuple(float(np.float32(x)) for x in K)
+    H, W = host_batch.shape[1:]
+    done = 0
+    t0 = time.perf_counter()
+    for b in range(host_batch.shape[0]):
+        oracle.estimate(host_batch[b], "depth_f32", K32, grad, agg, threads=threads)
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": round(done * H * W / dt / 1e6, 2), "unit": "Mpix/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d of the %d frames (%dx%d) of one batch, FP64, OpenMP over rows, %.1f s"
+                      % (done, host_batch.shape[0], H, W, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--grad", default="sobel")
+    ap.add_argument("--agg", default="median")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: frames are independent, so a multi-GPU run "
+              "would route whole frames to each GPU with no communication; "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2005_08165_amd import scenes as S
+    from paper_2005_08165_amd import sne
+
+    B, H, W = 64, 480, 640
+    NBUF = 4
+    cam = S.Camera(H, W, *S.INDOOR_K)
+    K = cam.as_tuple()
+    log("generating %d x %d frames" % (NBUF, B))
+    bufs = []
+    for j in range(NBUF):
+        raw = make_batch(torch, S, cam, range(1000 + j * B, 1000 + (j + 1) * B), "cuda")
+        nrm = torch.empty((B, 3, H, W), device="cuda")
+        msk = torch.empty((B, H, W), dtype=torch.uint8, device="cuda")
+        bufs.append((raw, nrm, msk))
+    torch.cuda.synchronize()
+
+    ctx = sne.Context(0)
+
+    def step(i):
+        raw, nrm, msk = bufs[i % NBUF]
+        sne.estimate_uniform(raw, K, "depth_f32", args.grad, args.agg, normals=nrm, mask=msk,
+                             ctx=ctx)
+
+    log("timing %d steps" % args.steps)
+    wall, ev = time_launches(torch, step, args.warmup, args.steps)
+    px = B * H * W
+    value = px * args.steps / wall / 1e6
+    bytes_per_launch = px * (4 + 12 + 1)
+    achieved = bytes_per_launch / (ev / args.steps) / 1e9
+    workload = "batch64_480x640_f32depth_%s_%s" % (args.grad, args.agg)
+    tile = ctx.get_tile(H, W, "depth_f32", args.grad, args.agg, "f32")
+    res = {
+        "metric": "normals Mpix/s (batched, 480x640)",
+        "value": round(value, 1),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": workload, "frames": B, "H": H, "W": W, "input": "f32 depth",
+                   "grad": args.grad, "agg": args.agg, "out": "f32 normals + u8 mask",
+                   "noise": "0.5% multiplicative Gaussian", "holes": 0.03,
+                   "rotated_buffers": NBUF},
+        "frames_per_s": round(B * args.steps / wall, 1),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": measured_traffic(workload),
+                     "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "kernel_us": round(ev / args.steps * 1e6, 2)},
+    }
+    if not args.no_plain:
+        log("plain single-frame launches")
+        res["plain_single_frame"] = [plain_single_frame(torch, S, sne, args.grad, args.agg),
+                                     plain_single_frame(torch, S, sne, "fd", "mean")]
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        host = bufs[0][0].cpu().numpy()
+        res["cpu_baseline"] = cpu_baseline(host, K, args.grad, args.agg)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

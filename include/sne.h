@@ -1,0 +1,185 @@
+/*
+ * sne.h - C ABI of the MI355X (gfx950) three-filters-to-normal library.
+ *
+ * The library turns depth or disparity images into unit surface normals with
+ * the three filters of Fan et al., "Three-Filters-to-Normal" (Sec. III):
+ * horizontal and vertical gradient filters on the inverse depth (eq.
+ * nx2_ny2_nz2) or on the disparity (eq. nx2_ny2_nz3) give n_x = f_x G_u and
+ * n_y = f_y G_v; a mean or median over the 8 neighbours of the candidates
+ * (dX n_x + dY n_y)/dZ gives n_z; the vector is then normalised.  Output
+ * conventions that the paper leaves open are fixed here:
+ *
+ *  - Coordinates: x right (+u), y down (+v), z forward; pixel centres at
+ *    integer (u, v); K = (fx, fy, u0, v0) in pixels (eq. intrinisc_matrix).
+ *  - The normal is the camera-facing unit vector -n'/|n'|, n' = (n_x, n_y,
+ *    n_z) of eq. nx2_ny2_nz2.  A window whose 8 neighbours all carry the raw
+ *    value of its centre gives (0, 0, -1) (the degenerate case of Sec. III);
+ *    so does |n'| = 0.
+ *  - A neighbour whose raw value equals that of the centre (dZ = 0) gives no
+ *    candidate; mean and median run over the m kept candidates; an even m
+ *    takes the mean of the two middle order statistics.
+ *  - Validity: a raw sample is valid iff finite and > 0 (uint16: > 0).  The
+ *    mask is 1 iff the pixel is interior (1 <= u <= W-2, 1 <= v <= H-2) and all
+ *    9 samples of its 3x3 window are valid.  Masked-out pixels get +0.0 in all
+ *    three channels and mask 0.
+ *  - Arithmetic is FP32 on the GPU whatever the storage type; FP16 output is
+ *    rounded to nearest even.
+ *
+ * Memory and ownership: every image, normal and mask pointer is a DEVICE
+ * pointer owned by the caller; the library never allocates, frees or keeps
+ * them.  Pitches are in ELEMENTS of the buffer's own type.  Normals are planar:
+ * channel c of row v, column u of a frame lives at
+ *     normals[c * plane + v * out_pitch + u],  plane = H * out_pitch.
+ * The mask pointer may be NULL (no mask written).
+ *
+ * Asynchrony: compute calls enqueue work on the given HIP stream (NULL = the
+ * default stream) and return; results are valid once that stream has
+ * synchronised.  A context is not thread-safe: use one per host thread.
+ *
+ * Errors: every call returns an int status.  SNE_OK (0) on success, a negative
+ * SNE_ERR_* code otherwise; arguments are checked before any HIP call, and an
+ * argument error leaves outputs untouched.  sne_status_string() names a code.
+ */
+#ifndef SNE_H_
+#define SNE_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SNE_OK 0
+#define SNE_ERR_ARG (-1)          /* bad pointer, size, enum or pitch        */
+#define SNE_ERR_UNSUPPORTED (-2)  /* valid request this build cannot serve   */
+#define SNE_ERR_BUDGET (-3)       /* request exceeds a configured capacity   */
+#define SNE_ERR_HIP (-4)          /* a HIP runtime call failed               */
+#define SNE_ERR_STATE (-5)        /* call not valid in the object's state    */
+#define SNE_ERR_FULL (-6)         /* queue full, retry later (serving)       */
+#define SNE_ERR_IO (-7)           /* file could not be read or written       */
+
+/* Pinhole intrinsics in pixels (eq. intrinisc_matrix).  Disparity input
+ * requires fx == fy (a rectified stereo pair, eq. z_d); the stereo baseline
+ * cancels from the normal and is not needed. */
+typedef struct {
+    float fx, fy, u0, v0;
+} sne_intrinsics;
+
+/* Raw input kinds. */
+#define SNE_DEPTH_F32 0      /* float depth, any unit                       */
+#define SNE_DEPTH_U16 1      /* uint16 depth, any unit (e.g. millimetres)   */
+#define SNE_DEPTH_F16 2      /* IEEE binary16 depth                         */
+#define SNE_DISPARITY_F32 3  /* float disparity in pixels                   */
+
+/* Gradient filters 1 and 2 (Sec. IV-B): K_x below, K_y = K_x^T, applied as a
+ * correlation.  FD is [-1 0 1]; Sobel rows [-1 0 1; -2 0 2; -1 0 1]; Scharr
+ * [-3 0 3; -10 0 10; -3 0 3]; Prewitt three rows of [-1 0 1]. */
+#define SNE_GRAD_FD 0
+#define SNE_GRAD_SOBEL 1
+#define SNE_GRAD_SCHARR 2
+#define SNE_GRAD_PREWITT 3
+
+/* Filter 3 (Phi of eq. nx2_ny2_nz2). */
+#define SNE_AGG_MEAN 0
+#define SNE_AGG_MEDIAN 1
+
+/* Normal storage type. */
+#define SNE_OUT_F32 0
+#define SNE_OUT_F16 1
+
+typedef struct sne_ctx sne_ctx;
+
+/* Create a context bound to HIP device `device`.  The context owns small
+ * device tables (descriptors, intrinsics, a tile counter) and the tile-shape
+ * cache of the autotuner.  *out is set to NULL on failure. */
+int sne_ctx_create(sne_ctx **out, int device);
+
+/* Wait for work the context enqueued, then free it.  NULL is accepted. */
+int sne_ctx_destroy(sne_ctx *ctx);
+
+/* One frame: `in` is [H][in_pitch] of the kind's element type; normals
+ * [3][H][out_pitch] of the out type; mask [H][mask_pitch] uint8 or NULL.
+ * H, W >= 1 (frames smaller than 3x3 have no interior: all masked).  ctx may
+ * be NULL (default tile shape).  One kernel launch. */
+int sne_estimate(sne_ctx *ctx, const void *in, int32_t H, int32_t W, int64_t in_pitch,
+                 const sne_intrinsics *K, int kind, int grad, int agg, int out_type,
+                 void *normals, int64_t out_pitch, uint8_t *mask, int64_t mask_pitch,
+                 void *stream);
+
+/* B frames of one size and one K in a single launch.  Frame b reads
+ * in + b * in_frame_stride and writes normals + b * out_frame_stride and
+ * mask + b * mask_frame_stride (strides in elements; an output frame stride
+ * must be at least 3 * H * out_pitch).  Bitwise identical, frame by frame, to
+ * B calls of sne_estimate. */
+int sne_estimate_uniform(sne_ctx *ctx, const void *in, int32_t B, int32_t H, int32_t W,
+                         int64_t in_pitch, int64_t in_frame_stride, const sne_intrinsics *K,
+                         int kind, int grad, int agg, int out_type, void *normals,
+                         int64_t out_pitch, int64_t out_frame_stride, uint8_t *mask,
+                         int64_t mask_pitch, int64_t mask_frame_stride, void *stream);
+
+/* Descriptor of one frame of an uneven batch (all device pointers). */
+typedef struct {
+    const void *in;          /* [H][in_pitch]                              */
+    void *normals;           /* [3][H][out_pitch]                          */
+    uint8_t *mask;           /* [H][mask_pitch] or NULL                    */
+    int32_t H, W;
+    int64_t in_pitch, out_pitch, mask_pitch;
+    int32_t k_index;         /* row of the context's intrinsics table      */
+    int32_t reserved;        /* must be 0                                  */
+} sne_frame;
+
+/* Copy n intrinsics records (host memory) into the context's device-resident
+ * table, replacing it; frames of sne_estimate_batched refer to its rows. */
+int sne_set_intrinsics_table(sne_ctx *ctx, const sne_intrinsics *K, int32_t n);
+
+/* n frames of any sizes (host array of descriptors) in ONE persistent launch:
+ * a grid sized to the GPU pulls tiles from a device counter until every tile
+ * of every frame is done.  All frames share kind, grad, agg and out type.
+ * Bitwise identical, frame by frame, to sne_estimate with the same K.
+ * The descriptor table is staged through pinned memory owned by the context,
+ * so the host array may be reused as soon as the call returns; a further call
+ * on the same context waits for the previous batch's staging copy. */
+int sne_estimate_batched(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int grad,
+                         int agg, int out_type, void *stream);
+
+/* Tile shape: each 64-lane wavefront covers `cols_per_lane * 64` columns by
+ * `rows` rows of a frame.  cols_per_lane is 1, 2 or 4 (vector width of the
+ * loads and stores); rows is 1..1024. */
+typedef struct {
+    int32_t cols_per_lane;
+    int32_t rows;
+} sne_tile;
+
+/* Force a tile shape for every later call on ctx (rows = 0 restores the
+ * autotuned/default choice).  A shape the frame's alignment cannot use falls
+ * back to a narrower cols_per_lane. */
+int sne_set_tile(sne_ctx *ctx, const sne_tile *tile);
+
+/* The tile shape ctx would use for an H x W frame of this variant. */
+int sne_get_tile(sne_ctx *ctx, int32_t H, int32_t W, int kind, int grad, int agg, int out_type,
+                 sne_tile *tile);
+
+/* Time every candidate tile shape on an H x W x B workload of this variant
+ * (synthetic planar input in scratch buffers the call allocates and frees),
+ * keep the fastest in ctx's cache for the frame-size class of H x W, and
+ * report it (tile may be NULL).  Synchronous; seconds at most. */
+int sne_autotune(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int grad, int agg,
+                 int out_type, sne_tile *tile);
+
+/* Save / load the tile-shape cache as text.  Entries recorded for another
+ * GPU architecture or library version are ignored on load. */
+int sne_autotune_save(const sne_ctx *ctx, const char *path);
+int sne_autotune_load(sne_ctx *ctx, const char *path);
+
+/* Human-readable name of a status code (static string). */
+const char *sne_status_string(int status);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int sne_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SNE_H_ */

@@ -1,0 +1,614 @@
+// sne_api.hip - host side of libsne: argument checks, tile-shape choice,
+// descriptor staging for uneven batches, the autotuner and the C ABI of
+// include/sne.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/sne.h"
+#include "sne_internal.h"
+
+namespace sne {
+namespace {
+
+constexpr int kVersion = 10000;  // 1.0.0
+constexpr int kSlots = 4;        // in-flight uneven batches per context
+
+struct TileKey {
+    int H, W, bclass, kind, grad, agg, out;
+    bool operator<(const TileKey &o) const {
+        return std::tie(H, W, bclass, kind, grad, agg, out) <
+               std::tie(o.H, o.W, o.bclass, o.kind, o.grad, o.agg, o.out);
+    }
+};
+struct TileChoice {
+    int px, rows, remap;
+};
+
+// Device tables of one in-flight uneven batch.
+struct Slot {
+    FrameDesc *d_frames = nullptr;
+    int32_t *d_start = nullptr;
+    int32_t *d_nstrips = nullptr;
+    int32_t *d_counter = nullptr;
+    void *h_stage = nullptr;  // pinned: frames | start | nstrips
+    size_t cap = 0;           // frames capacity
+    hipEvent_t done = nullptr;
+    bool used = false;
+};
+
+}  // namespace
+}  // namespace sne
+
+struct sne_ctx {
+    int device = 0;
+    int num_cu = 256;
+    std::string arch;
+    sne::TileChoice forced{0, 0, 0};
+    std::map<sne::TileKey, sne::TileChoice> cache;
+    sne_intrinsics *d_K = nullptr;
+    int32_t nK = 0;
+    sne::Slot slots[sne::kSlots];
+    int next_slot = 0;
+    int occ_blocks = 0;  // resident workgroups per CU for the persistent grid
+};
+
+namespace sne {
+namespace {
+
+bool valid_enum(int kind, int grad, int agg, int out) {
+    return kind >= SNE_DEPTH_F32 && kind <= SNE_DISPARITY_F32 && grad >= SNE_GRAD_FD &&
+           grad <= SNE_GRAD_PREWITT && agg >= SNE_AGG_MEAN && agg <= SNE_AGG_MEDIAN &&
+           out >= SNE_OUT_F32 && out <= SNE_OUT_F16;
+}
+
+bool valid_K(const sne_intrinsics *K, int kind) {
+    if (!K) return false;
+    if (!(std::isfinite(K->fx) && std::isfinite(K->fy) && std::isfinite(K->u0) &&
+          std::isfinite(K->v0)))
+        return false;
+    if (!(K->fx > 0.f && K->fy > 0.f)) return false;
+    if (kind == SNE_DISPARITY_F32 && K->fx != K->fy) return false;
+    return true;
+}
+
+size_t in_elem(int kind) { return kind == SNE_DEPTH_F32 || kind == SNE_DISPARITY_F32 ? 4 : 2; }
+size_t out_elem(int out) { return out == SNE_OUT_F32 ? 4 : 2; }
+
+// 3-row kernels as weights (side, centre) of the central differences.
+void grad_weights(int grad, float &wa, float &wb) {
+    switch (grad) {
+    case SNE_GRAD_SOBEL: wa = 1.f; wb = 2.f; break;
+    case SNE_GRAD_SCHARR: wa = 3.f; wb = 10.f; break;
+    case SNE_GRAD_PREWITT: wa = 1.f; wb = 1.f; break;
+    default: wa = 0.f; wb = 1.f; break;
+    }
+}
+
+bool aligned(const void *p, size_t bytes) { return ((uintptr_t)p % bytes) == 0; }
+
+// Widest columns-per-lane the buffers' alignment allows.
+int max_px(const void *in, const void *out, const uint8_t *mask, int W, int64_t in_pitch,
+           int64_t out_pitch, int64_t mask_pitch, int64_t in_fs, int64_t out_fs, int64_t mask_fs,
+           int64_t out_plane, int kind, int out_type) {
+    for (int px : {4, 2}) {
+        bool ok = (W % px == 0) && (in_pitch % px == 0) && (out_pitch % px == 0) &&
+                  (in_fs % px == 0) && (out_fs % px == 0) && (out_plane % px == 0) &&
+                  aligned(in, px * in_elem(kind)) && aligned(out, px * out_elem(out_type));
+        if (mask) ok = ok && (mask_pitch % px == 0) && (mask_fs % px == 0) && aligned(mask, px);
+        if (ok) return px;
+    }
+    return 1;
+}
+
+int batch_class(int64_t B) { return B <= 1 ? 0 : (B <= 8 ? 1 : 2); }
+
+// Heuristic tile shape when nothing is cached: fewest idle lanes in the last
+// strip, then enough wavefronts to cover every CU several times.
+TileChoice default_tile(const sne_ctx *ctx, int H, int W, int64_t B, int pxmax) {
+    int best = 1;
+    int64_t best_waste = -1;
+    for (int px : {4, 2, 1}) {
+        if (px > pxmax) continue;
+        const int64_t span = 64 * px;
+        const int64_t waste = ((W + span - 1) / span) * span - W;
+        if (best_waste < 0 || waste < best_waste) {
+            best = px;
+            best_waste = waste;
+        }
+    }
+    const int64_t nstrips = (W + 64 * best - 1) / (64 * best);
+    const int64_t target = (int64_t)(ctx ? ctx->num_cu : 256) * 16;  // wavefronts
+    int64_t rows = (B * H * nstrips) / std::max<int64_t>(target, 1);
+    rows = std::min<int64_t>(std::max<int64_t>(rows, 2), 32);
+    return TileChoice{best, (int)rows, 1};
+}
+
+TileChoice pick_tile(const sne_ctx *ctx, int H, int W, int64_t B, const Variant &v, int pxmax) {
+    if (ctx && ctx->forced.rows > 0) {
+        TileChoice t = ctx->forced;
+        while (t.px > pxmax) t.px >>= 1;
+        return t;
+    }
+    if (ctx) {
+        auto it = ctx->cache.find(TileKey{H, W, batch_class(B), v.kind, v.grad, v.agg, v.out});
+        if (it != ctx->cache.end()) {
+            TileChoice t = it->second;
+            while (t.px > pxmax) t.px >>= 1;
+            return t;
+        }
+    }
+    return default_tile(ctx, H, W, B, pxmax);
+}
+
+hipError_t launch_uniform(const Variant &v, const UniformArgs &a, int grid, hipStream_t s) {
+    switch (v.kind) {
+    case SNE_DEPTH_F32: return launch_uniform_f32(v, a, grid, s);
+    case SNE_DEPTH_U16: return launch_uniform_u16(v, a, grid, s);
+    case SNE_DEPTH_F16: return launch_uniform_f16(v, a, grid, s);
+    default: return launch_uniform_disp(v, a, grid, s);
+    }
+}
+
+hipError_t launch_batch(const Variant &v, const BatchArgs &a, int grid, hipStream_t s) {
+    switch (v.kind) {
+    case SNE_DEPTH_F32: return launch_batch_f32(v, a, grid, s);
+    case SNE_DEPTH_U16: return launch_batch_u16(v, a, grid, s);
+    case SNE_DEPTH_F16: return launch_batch_f16(v, a, grid, s);
+    default: return launch_batch_disp(v, a, grid, s);
+    }
+}
+
+__global__ void zero_counter(int32_t *c) { *c = 0; }
+
+FrameDesc make_desc(const void *in, void *out, uint8_t *mask, int H, int W, int64_t in_pitch,
+                    int64_t out_pitch, int64_t mask_pitch, const sne_intrinsics &K) {
+    FrameDesc f;
+    f.in = in;
+    f.out = out;
+    f.mask = mask;
+    f.in_pitch = in_pitch;
+    f.out_pitch = out_pitch;
+    f.out_plane = (int64_t)H * out_pitch;
+    f.mask_pitch = mask_pitch;
+    f.H = H;
+    f.W = W;
+    f.fx = K.fx;
+    f.fy = K.fy;
+    f.u0 = K.u0;
+    f.v0 = K.v0;
+    f.k_index = 0;
+    f.pad_ = 0;
+    return f;
+}
+
+int uniform_impl(sne_ctx *ctx, const void *in, int32_t B, int32_t H, int32_t W, int64_t in_pitch,
+                 int64_t in_fs, const sne_intrinsics *K, int kind, int grad, int agg, int out_type,
+                 void *normals, int64_t out_pitch, int64_t out_fs, uint8_t *mask,
+                 int64_t mask_pitch, int64_t mask_fs, void *stream, const TileChoice *force) {
+    if (!in || !normals || !valid_enum(kind, grad, agg, out_type) || !valid_K(K, kind))
+        return SNE_ERR_ARG;
+    if (B < 0 || H < 1 || W < 1 || in_pitch < W || out_pitch < W) return SNE_ERR_ARG;
+    if (mask && mask_pitch < W) return SNE_ERR_ARG;
+    const int64_t plane = (int64_t)H * out_pitch;
+    if (B > 1 && (in_fs < (int64_t)H * in_pitch || out_fs < 3 * plane ||
+                  (mask && mask_fs < (int64_t)H * mask_pitch)))
+        return SNE_ERR_ARG;
+    if (B == 0) return SNE_OK;
+    if (B == 1) {
+        in_fs = 0;
+        out_fs = 0;
+        mask_fs = 0;
+    }
+    Variant v{kind, grad, agg, out_type, 1};
+    const int pxmax = max_px(in, normals, mask, W, in_pitch, out_pitch, mask_pitch, in_fs, out_fs,
+                             mask_fs, plane, kind, out_type);
+    TileChoice t = force ? *force : pick_tile(ctx, H, W, B, v, pxmax);
+    if (t.px > pxmax || t.rows < 1) return SNE_ERR_ARG;
+    v.px = t.px;
+    UniformArgs a;
+    a.f = make_desc(in, normals, mask, H, W, in_pitch, out_pitch, mask_pitch, *K);
+    a.in_fstride = in_fs;
+    a.out_fstride = out_fs;
+    a.mask_fstride = mask_fs;
+    a.B = B;
+    a.nstrips = (W + 64 * t.px - 1) / (64 * t.px);
+    a.nbands = (H + t.rows - 1) / t.rows;
+    a.rows = t.rows;
+    const int64_t ntiles = (int64_t)B * a.nstrips * a.nbands;
+    if (ntiles > INT32_MAX - 4 * kWavesPerBlock) return SNE_ERR_BUDGET;
+    a.ntiles = (int32_t)ntiles;
+    a.xcd_remap = t.remap;
+    grad_weights(grad, a.wa, a.wb);
+    const int grid = (int)((ntiles + kWavesPerBlock - 1) / kWavesPerBlock);
+    if (ctx) hipSetDevice(ctx->device);
+    hipError_t e = launch_uniform(v, a, grid, (hipStream_t)stream);
+    return e == hipSuccess ? SNE_OK : SNE_ERR_HIP;
+}
+
+void free_slot(Slot &s) {
+    if (s.d_frames) hipFree(s.d_frames);
+    if (s.d_start) hipFree(s.d_start);
+    if (s.d_nstrips) hipFree(s.d_nstrips);
+    if (s.d_counter) hipFree(s.d_counter);
+    if (s.h_stage) hipHostFree(s.h_stage);
+    s = Slot{};
+}
+
+size_t stage_bytes(size_t cap) {
+    return cap * sizeof(FrameDesc) + (cap + 1) * sizeof(int32_t) + cap * sizeof(int32_t) + 64;
+}
+
+int ensure_slot(Slot &s, size_t n) {
+    if (!s.done && hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
+        return SNE_ERR_HIP;
+    if (n <= s.cap) return SNE_OK;
+    if (s.used) hipEventSynchronize(s.done);
+    hipEvent_t ev = s.done;
+    s.done = nullptr;
+    free_slot(s);
+    s.done = ev;
+    size_t cap = 64;
+    while (cap < n) cap *= 2;
+    if (hipMalloc(&s.d_frames, cap * sizeof(FrameDesc)) != hipSuccess ||
+        hipMalloc(&s.d_start, (cap + 1) * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&s.d_nstrips, cap * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&s.d_counter, sizeof(int32_t)) != hipSuccess ||
+        hipHostMalloc(&s.h_stage, stage_bytes(cap), hipHostMallocDefault) != hipSuccess) {
+        ev = s.done;
+        s.done = nullptr;
+        free_slot(s);
+        s.done = ev;
+        return SNE_ERR_HIP;
+    }
+    s.cap = cap;
+    return SNE_OK;
+}
+
+int batched_impl(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int grad, int agg,
+                 int out_type, void *stream, const TileChoice *force) {
+    if (!ctx || !frames || n < 0 || !valid_enum(kind, grad, agg, out_type)) return SNE_ERR_ARG;
+    if (n == 0) return SNE_OK;
+    // validate every descriptor before touching the GPU
+    int pxmax = 4;
+    int64_t total_px = 0;
+    int maxH = 0, maxW = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const sne_frame &f = frames[i];
+        if (!f.in || !f.normals || f.H < 1 || f.W < 1 || f.in_pitch < f.W ||
+            f.out_pitch < f.W || (f.mask && f.mask_pitch < f.W) || f.reserved != 0)
+            return SNE_ERR_ARG;
+        if (f.k_index < 0 || f.k_index >= ctx->nK) return SNE_ERR_ARG;
+        pxmax = std::min(pxmax, max_px(f.in, f.normals, f.mask, f.W, f.in_pitch, f.out_pitch,
+                                       f.mask_pitch, 0, 0, 0, (int64_t)f.H * f.out_pitch, kind,
+                                       out_type));
+        total_px += (int64_t)f.H * f.W;
+        maxH = std::max(maxH, (int)f.H);
+        maxW = std::max(maxW, (int)f.W);
+    }
+    Variant v{kind, grad, agg, out_type, 1};
+    TileChoice t = force ? *force : pick_tile(ctx, maxH, maxW, n, v, pxmax);
+    if (t.px > pxmax || t.rows < 1) return SNE_ERR_ARG;
+    v.px = t.px;
+    Slot &s = ctx->slots[ctx->next_slot];
+    ctx->next_slot = (ctx->next_slot + 1) % kSlots;
+    hipSetDevice(ctx->device);
+    int rc = ensure_slot(s, (size_t)n);
+    if (rc != SNE_OK) return rc;
+    if (s.used && hipEventSynchronize(s.done) != hipSuccess) return SNE_ERR_HIP;
+
+    FrameDesc *hf = (FrameDesc *)s.h_stage;
+    int32_t *hstart = (int32_t *)(hf + s.cap);
+    int32_t *hns = hstart + s.cap + 1;
+    int64_t tiles = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const sne_frame &f = frames[i];
+        const sne_intrinsics unused{1.f, 1.f, 0.f, 0.f};  // the kernel reads the table
+        hf[i] = make_desc(f.in, f.normals, f.mask, f.H, f.W, f.in_pitch, f.out_pitch,
+                          f.mask_pitch, unused);
+        hf[i].k_index = f.k_index;
+        const int ns = (f.W + 64 * t.px - 1) / (64 * t.px);
+        const int nb = (f.H + t.rows - 1) / t.rows;
+        hstart[i] = (int32_t)tiles;
+        hns[i] = ns;
+        tiles += (int64_t)ns * nb;
+        if (tiles > INT32_MAX / 2) return SNE_ERR_BUDGET;
+    }
+    hstart[n] = (int32_t)tiles;
+    hipStream_t st = (hipStream_t)stream;
+    if (hipMemcpyAsync(s.d_frames, hf, n * sizeof(FrameDesc), hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(s.d_start, hstart, (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(s.d_nstrips, hns, n * sizeof(int32_t), hipMemcpyHostToDevice, st) !=
+            hipSuccess)
+        return SNE_ERR_HIP;
+    hipLaunchKernelGGL(zero_counter, dim3(1), dim3(1), 0, st, s.d_counter);
+    BatchArgs a;
+    a.frames = s.d_frames;
+    a.tile_start = s.d_start;
+    a.nstrips = s.d_nstrips;
+    a.ktable = reinterpret_cast<const float4 *>(ctx->d_K);
+    a.counter = s.d_counter;
+    a.nframes = n;
+    a.ntiles = (int32_t)tiles;
+    a.rows = t.rows;
+    a.chunk = 1;
+    grad_weights(grad, a.wa, a.wb);
+    const int64_t want = (tiles + (int64_t)a.chunk * kWavesPerBlock - 1) /
+                         ((int64_t)a.chunk * kWavesPerBlock);
+    const int occ = ctx->occ_blocks > 0 ? ctx->occ_blocks : 8;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)ctx->num_cu * occ));
+    hipError_t e = launch_batch(v, a, grid, st);
+    if (e != hipSuccess) return SNE_ERR_HIP;
+    if (hipEventRecord(s.done, st) != hipSuccess) return SNE_ERR_HIP;
+    s.used = true;
+    (void)total_px;
+    return SNE_OK;
+}
+
+// Deterministic planar test pattern for the autotuner (depth or disparity).
+template <typename T>
+__global__ void fill_pattern(T *p, int64_t n, int W, int kind) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int u = (int)(i % W), v = (int)((i / W) % 100000);
+    float val = 1.5f + 0.0007f * u + 0.0003f * (v % 1000) + 0.01f * ((i * 2654435761u) % 7);
+    if (kind == SNE_DEPTH_U16)
+        p[i] = (T)(uint16_t)(val * 1000.f);
+    else if (kind == SNE_DEPTH_F16)
+        p[i] = (T)__builtin_bit_cast(uint16_t, (_Float16)val);
+    else if (kind == SNE_DISPARITY_F32)
+        p[i] = (T)(40.f / val);
+    else
+        p[i] = (T)val;
+}
+
+}  // namespace
+}  // namespace sne
+
+using namespace sne;
+
+extern "C" {
+
+int sne_version(void) { return kVersion; }
+
+const char *sne_status_string(int status) {
+    switch (status) {
+    case SNE_OK: return "ok";
+    case SNE_ERR_ARG: return "invalid argument";
+    case SNE_ERR_UNSUPPORTED: return "unsupported";
+    case SNE_ERR_BUDGET: return "over budget";
+    case SNE_ERR_HIP: return "HIP runtime error";
+    case SNE_ERR_STATE: return "invalid state";
+    case SNE_ERR_FULL: return "queue full";
+    case SNE_ERR_IO: return "file error";
+    default: return "unknown status";
+    }
+}
+
+int sne_ctx_create(sne_ctx **out, int device) {
+    if (!out) return SNE_ERR_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess) return SNE_ERR_HIP;
+    if (device < 0 || device >= ndev) return SNE_ERR_ARG;
+    if (hipSetDevice(device) != hipSuccess) return SNE_ERR_HIP;
+    sne_ctx *c = new sne_ctx();
+    c->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        c->num_cu = prop.multiProcessorCount;
+        c->arch = prop.gcnArchName;
+    }
+    c->occ_blocks = 8;
+    *out = c;
+    return SNE_OK;
+}
+
+int sne_ctx_destroy(sne_ctx *ctx) {
+    if (!ctx) return SNE_OK;
+    hipSetDevice(ctx->device);
+    for (auto &s : ctx->slots) {
+        if (s.used && s.done) hipEventSynchronize(s.done);
+        hipEvent_t ev = s.done;
+        free_slot(s);
+        if (ev) hipEventDestroy(ev);
+    }
+    if (ctx->d_K) hipFree(ctx->d_K);
+    delete ctx;
+    return SNE_OK;
+}
+
+int sne_estimate(sne_ctx *ctx, const void *in, int32_t H, int32_t W, int64_t in_pitch,
+                 const sne_intrinsics *K, int kind, int grad, int agg, int out_type,
+                 void *normals, int64_t out_pitch, uint8_t *mask, int64_t mask_pitch,
+                 void *stream) {
+    return uniform_impl(ctx, in, 1, H, W, in_pitch, 0, K, kind, grad, agg, out_type, normals,
+                        out_pitch, 0, mask, mask_pitch, 0, stream, nullptr);
+}
+
+int sne_estimate_uniform(sne_ctx *ctx, const void *in, int32_t B, int32_t H, int32_t W,
+                         int64_t in_pitch, int64_t in_frame_stride, const sne_intrinsics *K,
+                         int kind, int grad, int agg, int out_type, void *normals,
+                         int64_t out_pitch, int64_t out_frame_stride, uint8_t *mask,
+                         int64_t mask_pitch, int64_t mask_frame_stride, void *stream) {
+    return uniform_impl(ctx, in, B, H, W, in_pitch, in_frame_stride, K, kind, grad, agg, out_type,
+                        normals, out_pitch, out_frame_stride, mask, mask_pitch, mask_frame_stride,
+                        stream, nullptr);
+}
+
+int sne_set_intrinsics_table(sne_ctx *ctx, const sne_intrinsics *K, int32_t n) {
+    if (!ctx || !K || n < 1) return SNE_ERR_ARG;
+    for (int32_t i = 0; i < n; ++i)
+        if (!valid_K(&K[i], SNE_DEPTH_F32)) return SNE_ERR_ARG;
+    hipSetDevice(ctx->device);
+    // wait for batches that may still read the old table
+    for (auto &s : ctx->slots)
+        if (s.used && s.done) hipEventSynchronize(s.done);
+    if (n > ctx->nK) {
+        if (ctx->d_K) hipFree(ctx->d_K);
+        ctx->d_K = nullptr;
+        ctx->nK = 0;
+        if (hipMalloc(&ctx->d_K, n * sizeof(sne_intrinsics)) != hipSuccess) return SNE_ERR_HIP;
+    }
+    if (hipMemcpy(ctx->d_K, K, n * sizeof(sne_intrinsics), hipMemcpyHostToDevice) != hipSuccess)
+        return SNE_ERR_HIP;
+    ctx->nK = n;
+    return SNE_OK;
+}
+
+int sne_estimate_batched(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int grad,
+                         int agg, int out_type, void *stream) {
+    return batched_impl(ctx, frames, n, kind, grad, agg, out_type, stream, nullptr);
+}
+
+int sne_set_tile(sne_ctx *ctx, const sne_tile *tile) {
+    if (!ctx || !tile) return SNE_ERR_ARG;
+    if (tile->rows == 0) {
+        ctx->forced = TileChoice{0, 0, 0};
+        return SNE_OK;
+    }
+    if (!(tile->cols_per_lane == 1 || tile->cols_per_lane == 2 || tile->cols_per_lane == 4) ||
+        tile->rows < 1 || tile->rows > 1024)
+        return SNE_ERR_ARG;
+    ctx->forced = TileChoice{tile->cols_per_lane, tile->rows, 1};
+    return SNE_OK;
+}
+
+int sne_get_tile(sne_ctx *ctx, int32_t H, int32_t W, int kind, int grad, int agg, int out_type,
+                 sne_tile *tile) {
+    if (!tile || H < 1 || W < 1 || !valid_enum(kind, grad, agg, out_type)) return SNE_ERR_ARG;
+    Variant v{kind, grad, agg, out_type, 1};
+    TileChoice t = pick_tile(ctx, H, W, 1, v, 4);
+    tile->cols_per_lane = t.px;
+    tile->rows = t.rows;
+    return SNE_OK;
+}
+
+int sne_autotune(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int grad, int agg,
+                 int out_type, sne_tile *tile) {
+    if (!ctx || H < 1 || W < 1 || B < 1 || !valid_enum(kind, grad, agg, out_type))
+        return SNE_ERR_ARG;
+    hipSetDevice(ctx->device);
+    const int64_t npx = (int64_t)B * H * W;
+    void *in = nullptr, *out = nullptr;
+    uint8_t *mask = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = SNE_OK;
+    if (hipMalloc(&in, npx * in_elem(kind)) != hipSuccess ||
+        hipMalloc(&out, 3 * npx * out_elem(out_type)) != hipSuccess ||
+        hipMalloc(&mask, npx) != hipSuccess || hipStreamCreate(&st) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        rc = SNE_ERR_HIP;
+    }
+    TileChoice best{0, 0, 0};
+    if (rc == SNE_OK) {
+        const int threads = 256;
+        const int blocks = (int)((npx + threads - 1) / threads);
+        if (kind == SNE_DEPTH_F32 || kind == SNE_DISPARITY_F32)
+            hipLaunchKernelGGL(fill_pattern<float>, dim3(blocks), dim3(threads), 0, st,
+                               (float *)in, npx, W, kind);
+        else
+            hipLaunchKernelGGL(fill_pattern<uint16_t>, dim3(blocks), dim3(threads), 0, st,
+                               (uint16_t *)in, npx, W, kind);
+        sne_intrinsics K{(float)W, (float)W, (W - 1) * 0.5f, (H - 1) * 0.5f};
+        const int pxmax = max_px(in, out, mask, W, W, W, W, (int64_t)H * W, 3LL * H * W,
+                                 (int64_t)H * W, (int64_t)H * W, kind, out_type);
+        float best_ms = 1e30f;
+        const int rows_set[] = {2, 4, 8, 16, 32, 64};
+        for (int px : {1, 2, 4}) {
+            if (px > pxmax) continue;
+            for (int rows : rows_set) {
+                if (rows > 2 * H) continue;
+                for (int remap : {0, 1}) {
+                    TileChoice t{px, rows, remap};
+                    float samples[5];
+                    bool ok = true;
+                    for (int it = 0; it < 7 && ok; ++it) {
+                        hipEventRecord(e0, st);
+                        int r = uniform_impl(ctx, in, B, H, W, W, (int64_t)H * W, &K, kind, grad,
+                                             agg, out_type, out, W, 3LL * H * W, mask, W,
+                                             (int64_t)H * W, st, &t);
+                        hipEventRecord(e1, st);
+                        if (r != SNE_OK || hipEventSynchronize(e1) != hipSuccess) {
+                            ok = false;
+                            break;
+                        }
+                        float ms = 0.f;
+                        hipEventElapsedTime(&ms, e0, e1);
+                        if (it >= 2) samples[it - 2] = ms;
+                    }
+                    if (!ok) continue;
+                    std::sort(samples, samples + 5);
+                    if (samples[2] < best_ms) {
+                        best_ms = samples[2];
+                        best = t;
+                    }
+                }
+            }
+        }
+        if (best.rows == 0) rc = SNE_ERR_HIP;
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (st) hipStreamDestroy(st);
+    if (in) hipFree(in);
+    if (out) hipFree(out);
+    if (mask) hipFree(mask);
+    if (rc != SNE_OK) return rc;
+    ctx->cache[TileKey{H, W, batch_class(B), kind, grad, agg, out_type}] = best;
+    if (tile) {
+        tile->cols_per_lane = best.px;
+        tile->rows = best.rows;
+    }
+    return SNE_OK;
+}
+
+int sne_autotune_save(const sne_ctx *ctx, const char *path) {
+    if (!ctx || !path) return SNE_ERR_ARG;
+    FILE *f = std::fopen(path, "w");
+    if (!f) return SNE_ERR_IO;
+    std::fprintf(f, "# sne tile cache v1\n");
+    for (const auto &kv : ctx->cache) {
+        const TileKey &k = kv.first;
+        const TileChoice &t = kv.second;
+        std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d %d\n", ctx->arch.c_str(), kVersion, k.H,
+                     k.W, k.bclass, k.kind, k.grad, k.agg, k.out, t.px, t.rows, t.remap);
+    }
+    const bool ok = std::fclose(f) == 0;
+    return ok ? SNE_OK : SNE_ERR_IO;
+}
+
+int sne_autotune_load(sne_ctx *ctx, const char *path) {
+    if (!ctx || !path) return SNE_ERR_ARG;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return SNE_ERR_IO;
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+        if (line[0] == '#') continue;
+        char arch[128];
+        int ver, H, W, bc, kind, grad, agg, out, px, rows, remap;
+        if (std::sscanf(line, "%127s %d %d %d %d %d %d %d %d %d %d %d", arch, &ver, &H, &W, &bc,
+                        &kind, &grad, &agg, &out, &px, &rows, &remap) != 12)
+            continue;
+        if (ctx->arch != arch || ver != kVersion) continue;
+        if (!valid_enum(kind, grad, agg, out) || !(px == 1 || px == 2 || px == 4) || rows < 1 ||
+            rows > 1024)
+            continue;
+        ctx->cache[TileKey{H, W, bc, kind, grad, agg, out}] = TileChoice{px, rows, remap ? 1 : 0};
+    }
+    std::fclose(f);
+    return SNE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,298 @@
+"""Python binding of libsne (include/sne.h): argument marshalling only.
+
+Every step of the estimator runs in the HIP kernels of ``libsne.so``; this
+module converts torch tensors (device memory) and Python values into the C
+ABI's pointers, pitches and enums.  The raw ``sne_*`` functions mirror the C
+names one to one; ``Context`` and the tensor-level helpers below only
+allocate outputs with torch and fill in pitches.  If the library is missing
+every call raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Iterable, List, Optional, Sequence, Tuple
+
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libsne.so")
+HEADER = os.path.join(os.path.dirname(PKG), "include", "sne.h")
+
+SNE_OK = 0
+STATUS = {0: "SNE_OK", -1: "SNE_ERR_ARG", -2: "SNE_ERR_UNSUPPORTED", -3: "SNE_ERR_BUDGET",
+          -4: "SNE_ERR_HIP", -5: "SNE_ERR_STATE", -6: "SNE_ERR_FULL", -7: "SNE_ERR_IO"}
+
+KIND = {"depth_f32": 0, "depth_u16": 1, "depth_f16": 2, "disparity_f32": 3}
+KIND_DTYPE = {0: torch.float32, 1: torch.uint16, 2: torch.float16, 3: torch.float32}
+GRAD = {"fd": 0, "sobel": 1, "scharr": 2, "prewitt": 3}
+AGG = {"mean": 0, "median": 1}
+OUT = {"f32": 0, "f16": 1}
+OUT_DTYPE = {0: torch.float32, 1: torch.float16}
+
+
+class SneError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        super().__init__("%s failed: %s (%d)" % (fn, STATUS.get(status, "?"), status))
+        self.status = status
+
+
+class Intrinsics(ctypes.Structure):
+    _fields_ = [("fx", ctypes.c_float), ("fy", ctypes.c_float),
+                ("u0", ctypes.c_float), ("v0", ctypes.c_float)]
+
+
+class FrameDesc(ctypes.Structure):
+    _fields_ = [("input", ctypes.c_void_p), ("normals", ctypes.c_void_p),
+                ("mask", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("in_pitch", ctypes.c_int64), ("out_pitch", ctypes.c_int64),
+                ("mask_pitch", ctypes.c_int64), ("k_index", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class Tile(ctypes.Structure):
+    _fields_ = [("cols_per_lane", ctypes.c_int32), ("rows", ctypes.c_int32)]
+
+
+_lib = None
+_vp, _i32, _i64, _int = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int
+
+_SIGS = {
+    "sne_version": ([], _int),
+    "sne_status_string": ([_int], ctypes.c_char_p),
+    "sne_ctx_create": ([ctypes.POINTER(_vp), _int], _int),
+    "sne_ctx_destroy": ([_vp], _int),
+    "sne_estimate": ([_vp, _vp, _i32, _i32, _i64, ctypes.POINTER(Intrinsics), _int, _int, _int,
+                      _int, _vp, _i64, _vp, _i64, _vp], _int),
+    "sne_estimate_uniform": ([_vp, _vp, _i32, _i32, _i32, _i64, _i64, ctypes.POINTER(Intrinsics),
+                              _int, _int, _int, _int, _vp, _i64, _i64, _vp, _i64, _i64, _vp],
+                             _int),
+    "sne_set_intrinsics_table": ([_vp, ctypes.POINTER(Intrinsics), _i32], _int),
+    "sne_estimate_batched": ([_vp, ctypes.POINTER(FrameDesc), _i32, _int, _int, _int, _int, _vp],
+                             _int),
+    "sne_set_tile": ([_vp, ctypes.POINTER(Tile)], _int),
+    "sne_get_tile": ([_vp, _i32, _i32, _int, _int, _int, _int, ctypes.POINTER(Tile)], _int),
+    "sne_autotune": ([_vp, _i32, _i32, _i32, _int, _int, _int, _int, ctypes.POINTER(Tile)], _int),
+    "sne_autotune_save": ([_vp, ctypes.c_char_p], _int),
+    "sne_autotune_load": ([_vp, ctypes.c_char_p], _int),
+}
+
+
+def lib():
+    """Load libsne.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libsne.so not built: run `python -m paper_2005_08165_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def header_functions() -> List[str]:
+    """Names of the functions include/sne.h declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sne_[a-z_0-9]+)\s*\(", text)))
+
+
+def check(fn: str, status: int) -> None:
+    if status != SNE_OK:
+        raise SneError(fn, status)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _K(K: Sequence[float]) -> Intrinsics:
+    fx, fy, u0, v0 = (float(x) for x in K)
+    return Intrinsics(fx, fy, u0, v0)
+
+
+def _enum(table, key, what):
+    if isinstance(key, int):
+        return key
+    if key not in table:
+        raise ValueError("unknown %s %r" % (what, key))
+    return table[key]
+
+
+def _row_pitch(t: torch.Tensor) -> int:
+    """Row pitch (elements) of a [..., H, W] tensor with unit column stride."""
+    if t.stride(-1) != 1:
+        raise ValueError("images need a unit column stride")
+    return t.stride(-2)
+
+
+class Context:
+    """Owns an sne_ctx bound to one GPU."""
+
+    def __init__(self, device: int = 0):
+        self._h = ctypes.c_void_p()
+        check("sne_ctx_create", lib().sne_ctx_create(ctypes.byref(self._h), int(device)))
+        self.device = int(device)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().sne_ctx_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- tile shapes ---------------------------------------------------------
+    def set_tile(self, cols_per_lane: int = 0, rows: int = 0):
+        t = Tile(int(cols_per_lane), int(rows))
+        check("sne_set_tile", lib().sne_set_tile(self._h, ctypes.byref(t)))
+
+    def get_tile(self, H, W, kind="depth_f32", grad="fd", agg="mean", out="f32") -> Tuple[int, int]:
+        t = Tile()
+        check("sne_get_tile", lib().sne_get_tile(self._h, H, W, _enum(KIND, kind, "kind"),
+                                                 _enum(GRAD, grad, "grad"), _enum(AGG, agg, "agg"),
+                                                 _enum(OUT, out, "out"), ctypes.byref(t)))
+        return t.cols_per_lane, t.rows
+
+    def autotune(self, H, W, B=1, kind="depth_f32", grad="fd", agg="mean", out="f32"):
+        t = Tile()
+        check("sne_autotune", lib().sne_autotune(self._h, H, W, B, _enum(KIND, kind, "kind"),
+                                                 _enum(GRAD, grad, "grad"), _enum(AGG, agg, "agg"),
+                                                 _enum(OUT, out, "out"), ctypes.byref(t)))
+        return t.cols_per_lane, t.rows
+
+    def autotune_save(self, path: str):
+        check("sne_autotune_save", lib().sne_autotune_save(self._h, path.encode()))
+
+    def autotune_load(self, path: str):
+        check("sne_autotune_load", lib().sne_autotune_load(self._h, path.encode()))
+
+    def set_intrinsics_table(self, Ks: Sequence[Sequence[float]]):
+        arr = (Intrinsics * len(Ks))(*[_K(k) for k in Ks])
+        check("sne_set_intrinsics_table", lib().sne_set_intrinsics_table(self._h, arr, len(Ks)))
+
+    # -- compute -------------------------------------------------------------
+    def estimate(self, raw: torch.Tensor, K, kind="depth_f32", grad="fd", agg="mean", out="f32",
+                 normals: Optional[torch.Tensor] = None, mask: Optional[torch.Tensor] = None,
+                 want_mask: bool = True, stream=None):
+        return estimate(raw, K, kind, grad, agg, out, normals, mask, want_mask, stream, ctx=self)
+
+    def estimate_uniform(self, raw: torch.Tensor, K, kind="depth_f32", grad="fd", agg="mean",
+                         out="f32", normals=None, mask=None, want_mask=True, stream=None):
+        return estimate_uniform(raw, K, kind, grad, agg, out, normals, mask, want_mask, stream,
+                                ctx=self)
+
+    def estimate_batched(self, frames: Sequence[torch.Tensor], k_index: Sequence[int],
+                         kind="depth_u16", grad="fd", agg="mean", out="f16",
+                         normals: Optional[Sequence[torch.Tensor]] = None,
+                         masks: Optional[Sequence[Optional[torch.Tensor]]] = None, stream=None):
+        """One persistent launch over frames of any sizes.  Returns the lists
+        (normals, masks); outputs are allocated unless given."""
+        kind_i = _enum(KIND, kind, "kind")
+        out_i = _enum(OUT, out, "out")
+        n = len(frames)
+        if normals is None:
+            normals = [torch.empty((3,) + tuple(f.shape[-2:]), dtype=OUT_DTYPE[out_i],
+                                   device=f.device) for f in frames]
+        if masks is None:
+            masks = [torch.empty(tuple(f.shape[-2:]), dtype=torch.uint8, device=f.device)
+                     for f in frames]
+        descs = (FrameDesc * n)()
+        for i, f in enumerate(frames):
+            if f.dtype != KIND_DTYPE[kind_i]:
+                raise TypeError("frame %d: kind %s needs %s" % (i, kind, KIND_DTYPE[kind_i]))
+            H, W = f.shape[-2:]
+            m = masks[i]
+            descs[i] = FrameDesc(f.data_ptr(), normals[i].data_ptr(),
+                                 None if m is None else m.data_ptr(), H, W, _row_pitch(f),
+                                 _row_pitch(normals[i]), 0 if m is None else _row_pitch(m),
+                                 int(k_index[i]), 0)
+        check("sne_estimate_batched",
+              lib().sne_estimate_batched(self._h, descs, n, kind_i, _enum(GRAD, grad, "grad"),
+                                         _enum(AGG, agg, "agg"), out_i, _stream(stream)))
+        return normals, masks
+
+
+def _outputs(raw, out_i, normals, mask, want_mask):
+    shape = tuple(raw.shape[:-2]) + (3,) + tuple(raw.shape[-2:])
+    if normals is None:
+        normals = torch.empty(shape, dtype=OUT_DTYPE[out_i], device=raw.device)
+    if tuple(normals.shape) != shape or normals.dtype != OUT_DTYPE[out_i]:
+        raise ValueError("normals must be %s %s" % (shape, OUT_DTYPE[out_i]))
+    if normals.stride(-3) != raw.shape[-2] * _row_pitch(normals):
+        raise ValueError("normal channels must be H * row_pitch apart")
+    if mask is None and want_mask:
+        mask = torch.empty(tuple(raw.shape), dtype=torch.uint8, device=raw.device)
+    if mask is not None and (tuple(mask.shape) != tuple(raw.shape) or mask.dtype != torch.uint8):
+        raise ValueError("mask must be %s uint8" % (tuple(raw.shape),))
+    return normals, mask
+
+
+def estimate(raw: torch.Tensor, K, kind="depth_f32", grad="fd", agg="mean", out="f32",
+             normals=None, mask=None, want_mask=True, stream=None, ctx: Optional[Context] = None):
+    """sne_estimate on a [H, W] device tensor; returns (normals [3,H,W], mask)."""
+    kind_i, out_i = _enum(KIND, kind, "kind"), _enum(OUT, out, "out")
+    if raw.dim() != 2:
+        raise ValueError("expected [H, W]")
+    if raw.dtype != KIND_DTYPE[kind_i]:
+        raise TypeError("kind %s needs %s input" % (kind, KIND_DTYPE[kind_i]))
+    normals, mask = _outputs(raw, out_i, normals, mask, want_mask)
+    H, W = raw.shape
+    Kc = _K(K)
+    st = lib().sne_estimate(None if ctx is None else ctx.handle, raw.data_ptr(), H, W,
+                            _row_pitch(raw), ctypes.byref(Kc), kind_i, _enum(GRAD, grad, "grad"),
+                            _enum(AGG, agg, "agg"), out_i, normals.data_ptr(),
+                            _row_pitch(normals), _ptr(mask),
+                            0 if mask is None else _row_pitch(mask), _stream(stream))
+    check("sne_estimate", st)
+    return normals, mask
+
+
+def estimate_uniform(raw: torch.Tensor, K, kind="depth_f32", grad="fd", agg="mean", out="f32",
+                     normals=None, mask=None, want_mask=True, stream=None,
+                     ctx: Optional[Context] = None):
+    """sne_estimate_uniform on a [B, H, W] device tensor; returns
+    (normals [B,3,H,W], mask [B,H,W])."""
+    kind_i, out_i = _enum(KIND, kind, "kind"), _enum(OUT, out, "out")
+    if raw.dim() != 3:
+        raise ValueError("expected [B, H, W]")
+    if raw.dtype != KIND_DTYPE[kind_i]:
+        raise TypeError("kind %s needs %s input" % (kind, KIND_DTYPE[kind_i]))
+    normals, mask = _outputs(raw, out_i, normals, mask, want_mask)
+    B, H, W = raw.shape
+    Kc = _K(K)
+    st = lib().sne_estimate_uniform(
+        None if ctx is None else ctx.handle, raw.data_ptr(), B, H, W, _row_pitch(raw),
+        raw.stride(0), ctypes.byref(Kc), kind_i, _enum(GRAD, grad, "grad"),
+        _enum(AGG, agg, "agg"), out_i, normals.data_ptr(), _row_pitch(normals),
+        normals.stride(0), _ptr(mask), 0 if mask is None else _row_pitch(mask),
+        0 if mask is None else mask.stride(0), _stream(stream))
+    check("sne_estimate_uniform", st)
+    return normals, mask
+
+
+def status_string(code: int) -> str:
+    return lib().sne_status_string(int(code)).decode()
+
+
+def version() -> int:
+    return lib().sne_version()

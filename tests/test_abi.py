@@ -1,0 +1,92 @@
+"""The C ABI library loads, exports what include/sne.h declares, and rejects
+bad arguments with status codes before touching the GPU."""
+import ctypes
+
+import pytest
+
+from paper_2005_08165_amd import sne
+
+
+def test_exports_every_declared_function():
+    L = sne.lib()
+    names = sne.header_functions()
+    assert len(names) >= 13
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(sne._SIGS) <= set(names)
+
+
+def test_version_and_status_strings():
+    assert sne.version() == 10000
+    assert sne.status_string(0) == "ok"
+    assert sne.status_string(-1) == "invalid argument"
+    assert sne.status_string(12345) == "unknown status"
+
+
+def _K(fx=500.0, fy=500.0, u0=10.0, v0=10.0):
+    return sne.Intrinsics(fx, fy, u0, v0)
+
+
+FAKE = 0x10000  # never dereferenced: every call below fails validation first
+
+
+@pytest.mark.parametrize("case", [
+    dict(inp=None), dict(normals=None), dict(H=0), dict(W=0), dict(in_pitch=5),
+    dict(out_pitch=5), dict(mask_pitch=5), dict(kind=7), dict(grad=-1), dict(agg=2),
+    dict(out=2), dict(K=_K(fx=0.0)), dict(K=_K(fy=-1.0)), dict(K=_K(u0=float("nan"))),
+    dict(K=_K(fx=float("inf"))), dict(kind=3, K=_K(fx=500.0, fy=501.0)), dict(Knull=True),
+])
+def test_estimate_argument_errors(case):
+    L = sne.lib()
+    a = dict(inp=FAKE, H=10, W=10, in_pitch=10, kind=0, grad=0, agg=0, out=0, normals=FAKE,
+             out_pitch=10, mask=FAKE, mask_pitch=10, K=_K())
+    a.update(case)
+    K = None if case.get("Knull") else ctypes.byref(a["K"])
+    rc = L.sne_estimate(None, a["inp"], a["H"], a["W"], a["in_pitch"], K, a["kind"], a["grad"],
+                        a["agg"], a["out"], a["normals"], a["out_pitch"], a["mask"],
+                        a["mask_pitch"], None)
+    assert rc == -1
+
+
+def test_uniform_argument_errors():
+    L = sne.lib()
+    K = _K()
+    # frame strides too small for B > 1
+    assert L.sne_estimate_uniform(None, FAKE, 4, 10, 10, 10, 50, ctypes.byref(K), 0, 0, 0, 0,
+                                  FAKE, 10, 300, FAKE, 10, 100, None) == -1
+    assert L.sne_estimate_uniform(None, FAKE, 4, 10, 10, 10, 100, ctypes.byref(K), 0, 0, 0, 0,
+                                  FAKE, 10, 299, FAKE, 10, 100, None) == -1
+    assert L.sne_estimate_uniform(None, FAKE, -1, 10, 10, 10, 100, ctypes.byref(K), 0, 0, 0, 0,
+                                  FAKE, 10, 300, FAKE, 10, 100, None) == -1
+    # B = 0 is a valid empty batch: nothing is launched
+    assert L.sne_estimate_uniform(None, FAKE, 0, 10, 10, 10, 100, ctypes.byref(K), 0, 0, 0, 0,
+                                  FAKE, 10, 300, FAKE, 10, 100, None) == 0
+
+
+def test_null_context_errors():
+    L = sne.lib()
+    t = sne.Tile(2, 8)
+    assert L.sne_set_tile(None, ctypes.byref(t)) == -1
+    assert L.sne_estimate_batched(None, None, 1, 0, 0, 0, 0, None) == -1
+    assert L.sne_set_intrinsics_table(None, None, 1) == -1
+    assert L.sne_autotune(None, 10, 10, 1, 0, 0, 0, 0, None) == -1
+    assert L.sne_autotune_save(None, b"/tmp/x") == -1
+    assert L.sne_ctx_destroy(None) == 0
+    assert L.sne_ctx_create(None, 0) == -1
+    assert L.sne_get_tile(None, 0, 10, 0, 0, 0, 0, ctypes.byref(t)) == -1
+
+
+def test_default_tile_shape_without_context():
+    L = sne.lib()
+    t = sne.Tile()
+    assert L.sne_get_tile(None, 480, 640, 0, 0, 0, 0, ctypes.byref(t)) == 0
+    assert t.cols_per_lane in (1, 2, 4) and 1 <= t.rows <= 1024
+    # 640 = 5 x 128: two columns per lane leaves no idle lane
+    assert t.cols_per_lane == 2
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(sne, "_lib", None)
+    monkeypatch.setattr(sne, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        sne.lib()
