@@ -99,6 +99,17 @@ def plain_single_frame(torch, S, sne, grad, agg, reps=200):
             "latency_us_p99": round(lat[int(len(lat) * 0.99) - 1] * 1e6, 1)}
 
 
+def copy_calibration(torch, nbytes=1 << 30, reps=10):
+    """A plain device-to-device copy of known size: its rate is the
+    achievable-bandwidth reference, and its PMC byte counts (read in the same
+    profiling passes) scale the stencil's FETCH_SIZE / WRITE_SIZE."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    wall, ev = time_launches(torch, lambda i: b.copy_(a), 2, reps)
+    return {"bytes_per_copy": 2 * nbytes, "GBs": round(2 * nbytes * reps / ev / 1e9, 1),
+            "us_per_copy": round(ev / reps * 1e6, 1)}
+
+
 def cpu_baseline(host_batch, K, grad, agg, budget_s=20.0):
     """The FP64 oracle, as it stands, on the host's cores over a bounded
     sample of the same workload."""
@@ -198,6 +209,8 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_per_launch,
                      "kernel_us": round(ev / args.steps * 1e6, 2)},
     }
+    log("copy calibration")
+    res["copy_calibration"] = copy_calibration(torch)
     if not args.no_plain:
         log("plain single-frame launches")
         res["plain_single_frame"] = [plain_single_frame(torch, S, sne, args.grad, args.agg),

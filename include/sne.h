@@ -172,6 +172,116 @@ int sne_autotune(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int gr
 int sne_autotune_save(const sne_ctx *ctx, const char *path);
 int sne_autotune_load(sne_ctx *ctx, const char *path);
 
+/* ------------------------------------------------------------------------
+ * Serving loop.  A server owns an output arena of `hbm_budget_bytes` device
+ * memory and a scheduler thread.  Submitted requests (one device-resident
+ * frame each, with the row of the context's intrinsics table that describes
+ * its sensor) are admitted in arrival order while their outputs fit in the
+ * arena, grouped into batches whenever one of `max_inflight` slots is free,
+ * and each batch runs as one persistent uneven-batch launch on the slot's
+ * own stream: batches overlap on the GPU and requests arriving meanwhile
+ * join the next batch (continuous batching).  Results stay in the arena
+ * until released.  Every request's result is bitwise identical to
+ * sne_estimate of the same frame.  The scheduling policy is not specified by
+ * the paper, which times single frames only (Sec. IV-C). */
+typedef struct sne_server sne_server;
+
+typedef struct {
+    int32_t kind, grad, agg, out_type;  /* method variant, as for sne_estimate */
+    int32_t max_inflight;               /* concurrent batches, 1..8          */
+    int32_t max_batch_frames;           /* 1..65536                          */
+    int64_t max_batch_pixels;           /* a lone larger frame still runs    */
+    int64_t hbm_budget_bytes;           /* output arena (normals + masks)    */
+    int64_t queue_capacity;             /* waiting requests before SNE_ERR_FULL */
+    int32_t use_graphs;                 /* 1: replay a captured hipGraph per batch */
+    int32_t reserved;                   /* must be 0 */
+} sne_server_config;
+
+typedef struct {
+    const void *in;        /* device frame [H][in_pitch] of the server's kind */
+    int32_t H, W;
+    int64_t in_pitch;      /* elements */
+    int32_t stream_id;     /* sensor stream = row of the intrinsics table    */
+    int32_t reserved;      /* must be 0 */
+    double t_arrival;      /* seconds on the server clock; < 0: now          */
+} sne_request;
+
+typedef struct {
+    uint64_t ticket;
+    int32_t status;        /* SNE_OK or the error that failed the batch      */
+    int32_t stream_id;
+    void *normals;         /* [3][H][W] of the out type, inside the arena    */
+    uint8_t *mask;         /* [H][W] inside the arena                        */
+    int32_t H, W;
+    double t_arrival, t_launch, t_done;  /* server clock, seconds            */
+} sne_completion;
+
+typedef struct {
+    uint64_t submitted, completed, failed, rejected_full, rejected_budget, batches;
+    double mean_batch_frames;
+    double latency_p50, latency_p90, latency_p99, latency_p999, latency_max; /* s */
+    double mpix_per_s, frames_per_s;   /* first arrival .. last completion   */
+    int64_t arena_free_bytes;
+} sne_server_stats;
+
+/* Create a server on ctx (which must outlive it).  The frames' intrinsics are
+ * read from ctx's table (sne_set_intrinsics_table) when each batch runs. */
+int sne_server_create(sne_server **out, sne_ctx *ctx, const sne_server_config *cfg);
+/* Thread-safe.  SNE_ERR_BUDGET: the frame's outputs exceed the whole arena;
+ * SNE_ERR_FULL: queue_capacity requests are already waiting (retry). */
+int sne_server_submit(sne_server *srv, const sne_request *req, uint64_t *ticket);
+/* Up to max finished requests (oldest first); *n receives the count. */
+int sne_server_poll(sne_server *srv, sne_completion *out, int32_t max, int32_t *n);
+/* Hand a finished request's outputs back to the arena (SNE_ERR_STATE while
+ * it is still queued or running). */
+int sne_server_release(sne_server *srv, uint64_t ticket);
+/* Wait until nothing is queued or running (SNE_ERR_STATE on timeout). */
+int sne_server_drain(sne_server *srv, double timeout_s);
+int sne_server_get_stats(sne_server *srv, sne_server_stats *st);
+int sne_server_reset_stats(sne_server *srv);
+/* Seconds since the server was created (the clock of t_arrival / t_done). */
+double sne_server_now(const sne_server *srv);
+/* Drain, stop the scheduler thread, free the arena.  NULL is accepted. */
+int sne_server_destroy(sne_server *srv);
+
+/* Open-loop load: n_streams independent Poisson processes totalling
+ * total_rate frames/s for duration_s, submitted by n_producers threads at
+ * their scheduled times (latency counts from the scheduled arrival).  Frame
+ * k of stream s is frames[s * ring + k % ring] with size H[s] x W[s] and
+ * row pitch pitch[s]; stream s uses intrinsics row s.  A client thread
+ * releases results as they complete.  Fills *st for this run. */
+typedef struct {
+    int32_t n_streams;
+    int32_t n_producers;
+    double total_rate;
+    double duration_s;
+    uint64_t seed;
+    const void *const *frames;
+    int32_t ring;
+    int32_t reserved;
+    const int32_t *H, *W;
+    const int64_t *pitch;
+} sne_loadgen_config;
+int sne_server_run_open_loop(sne_server *srv, const sne_loadgen_config *cfg,
+                             sne_server_stats *st);
+
+/* Capacity model: the same scheduler against a GPU that processes batches in
+ * launch order at gpu_pixels_per_s after batch_overhead_s, on a simulated
+ * clock with ticks of tick_s (0: 10 us).  Host-only; for planning a
+ * configuration before running it. */
+typedef struct {
+    int32_t n_streams;
+    int32_t max_inflight;
+    int32_t max_batch_frames;
+    int32_t reserved;
+    int64_t max_batch_pixels;   /* <= 0: unlimited */
+    int64_t budget_bytes;
+    double total_rate, duration_s, gpu_pixels_per_s, batch_overhead_s, tick_s;
+    uint64_t seed;
+    const int32_t *H, *W;       /* per stream */
+} sne_sim_config;
+int sne_sched_simulate(const sne_sim_config *cfg, sne_server_stats *st);
+
 /* Human-readable name of a status code (static string). */
 const char *sne_status_string(int status);
 

@@ -7,62 +7,12 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
-#include <map>
-#include <mutex>
-#include <string>
-#include <tuple>
 #include <vector>
 
-#include "../../include/sne.h"
-#include "sne_internal.h"
+
+#include "sne_host.h"
 
 namespace sne {
-namespace {
-
-constexpr int kVersion = 10000;  // 1.0.0
-constexpr int kSlots = 4;        // in-flight uneven batches per context
-
-struct TileKey {
-    int H, W, bclass, kind, grad, agg, out;
-    bool operator<(const TileKey &o) const {
-        return std::tie(H, W, bclass, kind, grad, agg, out) <
-               std::tie(o.H, o.W, o.bclass, o.kind, o.grad, o.agg, o.out);
-    }
-};
-struct TileChoice {
-    int px, rows, remap;
-};
-
-// Device tables of one in-flight uneven batch.
-struct Slot {
-    FrameDesc *d_frames = nullptr;
-    int32_t *d_start = nullptr;
-    int32_t *d_nstrips = nullptr;
-    int32_t *d_counter = nullptr;
-    void *h_stage = nullptr;  // pinned: frames | start | nstrips
-    size_t cap = 0;           // frames capacity
-    hipEvent_t done = nullptr;
-    bool used = false;
-};
-
-}  // namespace
-}  // namespace sne
-
-struct sne_ctx {
-    int device = 0;
-    int num_cu = 256;
-    std::string arch;
-    sne::TileChoice forced{0, 0, 0};
-    std::map<sne::TileKey, sne::TileChoice> cache;
-    sne_intrinsics *d_K = nullptr;
-    int32_t nK = 0;
-    sne::Slot slots[sne::kSlots];
-    int next_slot = 0;
-    int occ_blocks = 0;  // resident workgroups per CU for the persistent grid
-};
-
-namespace sne {
-namespace {
 
 bool valid_enum(int kind, int grad, int agg, int out) {
     return kind >= SNE_DEPTH_F32 && kind <= SNE_DISPARITY_F32 && grad >= SNE_GRAD_FD &&
@@ -169,6 +119,11 @@ hipError_t launch_batch(const Variant &v, const BatchArgs &a, int grid, hipStrea
 
 __global__ void zero_counter(int32_t *c) { *c = 0; }
 
+hipError_t launch_zero_counter(int32_t *counter, hipStream_t s) {
+    hipLaunchKernelGGL(zero_counter, dim3(1), dim3(1), 0, s, counter);
+    return hipGetLastError();
+}
+
 FrameDesc make_desc(const void *in, void *out, uint8_t *mask, int H, int W, int64_t in_pitch,
                     int64_t out_pitch, int64_t mask_pitch, const sne_intrinsics &K) {
     FrameDesc f;
@@ -190,6 +145,8 @@ FrameDesc make_desc(const void *in, void *out, uint8_t *mask, int H, int W, int6
     return f;
 }
 
+namespace {
+
 int uniform_impl(sne_ctx *ctx, const void *in, int32_t B, int32_t H, int32_t W, int64_t in_pitch,
                  int64_t in_fs, const sne_intrinsics *K, int kind, int grad, int agg, int out_type,
                  void *normals, int64_t out_pitch, int64_t out_fs, uint8_t *mask,
@@ -208,6 +165,8 @@ int uniform_impl(sne_ctx *ctx, const void *in, int32_t B, int32_t H, int32_t W, 
         out_fs = 0;
         mask_fs = 0;
     }
+    // the kernels address one frame's input with 32-bit byte offsets
+    if ((int64_t)(H + 2) * in_pitch * (int64_t)in_elem(kind) >= INT32_MAX) return SNE_ERR_UNSUPPORTED;
     Variant v{kind, grad, agg, out_type, 1};
     const int pxmax = max_px(in, normals, mask, W, in_pitch, out_pitch, mask_pitch, in_fs, out_fs,
                              mask_fs, plane, kind, out_type);
@@ -287,6 +246,8 @@ int batched_impl(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int
             f.out_pitch < f.W || (f.mask && f.mask_pitch < f.W) || f.reserved != 0)
             return SNE_ERR_ARG;
         if (f.k_index < 0 || f.k_index >= ctx->nK) return SNE_ERR_ARG;
+        if ((int64_t)(f.H + 2) * f.in_pitch * (int64_t)in_elem(kind) >= INT32_MAX)
+            return SNE_ERR_UNSUPPORTED;
         pxmax = std::min(pxmax, max_px(f.in, f.normals, f.mask, f.W, f.in_pitch, f.out_pitch,
                                        f.mask_pitch, 0, 0, 0, (int64_t)f.H * f.out_pitch, kind,
                                        out_type));
@@ -331,13 +292,14 @@ int batched_impl(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int
         hipMemcpyAsync(s.d_nstrips, hns, n * sizeof(int32_t), hipMemcpyHostToDevice, st) !=
             hipSuccess)
         return SNE_ERR_HIP;
-    hipLaunchKernelGGL(zero_counter, dim3(1), dim3(1), 0, st, s.d_counter);
+    if (launch_zero_counter(s.d_counter, st) != hipSuccess) return SNE_ERR_HIP;
     BatchArgs a;
     a.frames = s.d_frames;
     a.tile_start = s.d_start;
     a.nstrips = s.d_nstrips;
     a.ktable = reinterpret_cast<const float4 *>(ctx->d_K);
     a.counter = s.d_counter;
+    a.counts = nullptr;
     a.nframes = n;
     a.ntiles = (int32_t)tiles;
     a.rows = t.rows;

@@ -1,0 +1,72 @@
+// sne_host.h - host-side internals shared by the units of libsne (context,
+// tile-shape choice, launch helpers).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <tuple>
+
+#include "../../include/sne.h"
+#include "sne_internal.h"
+
+namespace sne {
+
+constexpr int kVersion = 10000;  // 1.0.0
+constexpr int kSlots = 4;        // in-flight uneven batches per context
+
+struct TileKey {
+    int H, W, bclass, kind, grad, agg, out;
+    bool operator<(const TileKey &o) const {
+        return std::tie(H, W, bclass, kind, grad, agg, out) <
+               std::tie(o.H, o.W, o.bclass, o.kind, o.grad, o.agg, o.out);
+    }
+};
+struct TileChoice {
+    int px, rows, remap;
+};
+
+// Device tables of one in-flight uneven batch.
+struct Slot {
+    FrameDesc *d_frames = nullptr;
+    int32_t *d_start = nullptr;
+    int32_t *d_nstrips = nullptr;
+    int32_t *d_counter = nullptr;
+    void *h_stage = nullptr;  // pinned: frames | start | nstrips
+    size_t cap = 0;           // frames capacity
+    hipEvent_t done = nullptr;
+    bool used = false;
+};
+
+bool valid_enum(int kind, int grad, int agg, int out);
+bool valid_K(const sne_intrinsics *K, int kind);
+size_t in_elem(int kind);
+size_t out_elem(int out);
+void grad_weights(int grad, float &wa, float &wb);
+int max_px(const void *in, const void *out, const uint8_t *mask, int W, int64_t in_pitch,
+           int64_t out_pitch, int64_t mask_pitch, int64_t in_fs, int64_t out_fs, int64_t mask_fs,
+           int64_t out_plane, int kind, int out_type);
+FrameDesc make_desc(const void *in, void *out, uint8_t *mask, int H, int W, int64_t in_pitch,
+                    int64_t out_pitch, int64_t mask_pitch, const sne_intrinsics &K);
+hipError_t launch_batch(const Variant &v, const BatchArgs &a, int grid, hipStream_t s);
+hipError_t launch_zero_counter(int32_t *counter, hipStream_t s);
+
+}  // namespace sne
+
+struct sne_ctx {
+    int device = 0;
+    int num_cu = 256;
+    std::string arch;
+    sne::TileChoice forced{0, 0, 0};
+    std::map<sne::TileKey, sne::TileChoice> cache;
+    sne_intrinsics *d_K = nullptr;
+    int32_t nK = 0;
+    sne::Slot slots[sne::kSlots];
+    int next_slot = 0;
+    int occ_blocks = 0;  // resident workgroups per CU for the persistent grid
+};
+
+namespace sne {
+TileChoice pick_tile(const sne_ctx *ctx, int H, int W, int64_t B, const Variant &v, int pxmax);
+}  // namespace sne

@@ -42,6 +42,8 @@ struct BatchArgs {
     const int32_t *nstrips;    // [nframes]
     const float4 *ktable;      // device-resident intrinsics (fx, fy, u0, v0)
     int32_t *counter;          // tile queue head, 0 at launch
+    const int32_t *counts;     // if set: {nframes, ntiles} in device memory
+                               // (a captured graph replays with new counts)
     int32_t nframes, ntiles, rows, chunk;
     float wa, wb;
 };

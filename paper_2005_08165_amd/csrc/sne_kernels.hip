@@ -88,19 +88,54 @@ template <int KIND, int PX> struct RawRow {
     typename Raw<KIND>::T h;  // halo sample: lane 0 left, lane 63 right
 };
 
-// Issue the loads of row r (zeros outside the frame).
+// A frame's input as a buffer resource: loads outside [0, bytes) return 0
+// without touching memory, which covers the rows above and below the frame,
+// the columns past its width and the halo of lanes that load none.
+struct InBuf {
+    __amdgpu_buffer_rsrc_t rsrc;
+    int pitch_bytes;
+};
+
+__device__ __forceinline__ InBuf make_inbuf(const void *base, int64_t pitch, int H, int elem) {
+    InBuf b;
+    b.rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0,
+                                               (int)((int64_t)H * pitch * elem), 0x00020000);
+    b.pitch_bytes = (int)(pitch * elem);
+    return b;
+}
+
+constexpr int kOOB = 0x7fffffff;  // a byte offset past any frame
+
+template <typename T, int N> __device__ __forceinline__ Vec<T, N> buf_load(const InBuf &b, int off);
+template <> __device__ __forceinline__ Vec<float, 1> buf_load<float, 1>(const InBuf &b, int off) {
+    return __builtin_bit_cast(Vec<float, 1>, __builtin_amdgcn_raw_buffer_load_b32(b.rsrc, off, 0, 0));
+}
+template <> __device__ __forceinline__ Vec<float, 2> buf_load<float, 2>(const InBuf &b, int off) {
+    return __builtin_bit_cast(Vec<float, 2>, __builtin_amdgcn_raw_buffer_load_b64(b.rsrc, off, 0, 0));
+}
+template <> __device__ __forceinline__ Vec<float, 4> buf_load<float, 4>(const InBuf &b, int off) {
+    return __builtin_bit_cast(Vec<float, 4>, __builtin_amdgcn_raw_buffer_load_b128(b.rsrc, off, 0, 0));
+}
+template <> __device__ __forceinline__ Vec<uint16_t, 1> buf_load<uint16_t, 1>(const InBuf &b, int off) {
+    return __builtin_bit_cast(Vec<uint16_t, 1>, __builtin_amdgcn_raw_buffer_load_b16(b.rsrc, off, 0, 0));
+}
+template <> __device__ __forceinline__ Vec<uint16_t, 2> buf_load<uint16_t, 2>(const InBuf &b, int off) {
+    return __builtin_bit_cast(Vec<uint16_t, 2>, __builtin_amdgcn_raw_buffer_load_b32(b.rsrc, off, 0, 0));
+}
+template <> __device__ __forceinline__ Vec<uint16_t, 4> buf_load<uint16_t, 4>(const InBuf &b, int off) {
+    return __builtin_bit_cast(Vec<uint16_t, 4>, __builtin_amdgcn_raw_buffer_load_b64(b.rsrc, off, 0, 0));
+}
+
+// Issue the loads of row r; everything outside the frame reads as 0.
+// col_off / halo_off: this lane's byte offsets within a row, kOOB-based when
+// the lane loads nothing.
 template <int KIND, int PX>
-__device__ __forceinline__ void load_raw(const FrameDesc &f, int r, int col, int hcol,
-                                         bool halo_lane, RawRow<KIND, PX> &o) {
+__device__ __forceinline__ void load_raw(const InBuf &b, int r, int col_off, int halo_off,
+                                         RawRow<KIND, PX> &o) {
     using T = typename Raw<KIND>::T;
-#pragma unroll
-    for (int k = 0; k < PX; ++k) o.x.v[k] = T(0);
-    o.h = T(0);
-    if (r >= 0 && r < f.H) {
-        const T *row = static_cast<const T *>(f.in) + (int64_t)r * f.in_pitch;
-        if (col < f.W) o.x = *reinterpret_cast<const Vec<T, PX> *>(row + col);
-        if (halo_lane && hcol >= 0 && hcol < f.W) o.h = row[hcol];
-    }
+    const int row = r * b.pitch_bytes;  // negative or past the end -> out of range
+    o.x = buf_load<T, PX>(b, col_off == kOOB ? kOOB : row + col_off);
+    o.h = buf_load<T, 1>(b, halo_off == kOOB ? kOOB : row + halo_off).v[0];
 }
 
 // Per-row state.  Index i of z/s is column (lane base + i - 1): 0 and PX+1
@@ -187,144 +222,197 @@ template <> struct MaskWord<1> { using T = uint8_t; };
 template <> struct MaskWord<2> { using T = uint16_t; };
 template <> struct MaskWord<4> { using T = uint32_t; };
 
-// One tile: columns [c0, c0 + 64 PX) x rows [r0, r1) of frame f.
+// Row r of the three-row window together with the pair reciprocals between
+// it and row r + 1.
+template <int PX> struct RowState {
+    Row<PX> row;
+    Pairs<PX> below;
+};
+
+__device__ __forceinline__ float median_pair(float (&t)[8], bool odd) {
+    sort4(t[0], t[1], t[2], t[3]);
+    sort4(t[4], t[5], t[6], t[7]);
+    // merged order statistics 3 and 4 (0-based) of two sorted quads
+    const float x3 = fminf(fminf(fminf(t[7], fmaxf(t[0], t[6])),
+                                 fminf(fmaxf(t[1], t[5]), fmaxf(t[2], t[4]))),
+                           t[3]);
+    const float x4 = fminf(fminf(fmaxf(t[0], t[7]), fmaxf(t[1], t[6])),
+                           fminf(fmaxf(t[2], t[5]), fmaxf(t[3], t[4])));
+    return odd ? x3 : 0.5f * (x3 + x4);
+}
+
+// Median of the kept candidates.  t: 8 candidates in slot order; zj/zc: raw
+// values deciding which slots are left out.  `general` pads left-out slots
+// alternately +inf / -inf; otherwise all 8 are kept.  *none: nothing kept.
+// The network is spelled out in each branch so that the fast path sorts
+// values the compiler knows to be canonical.
+__device__ __forceinline__ float median8(float (&t)[8], const float (&zj)[8], float zc,
+                                         bool general, bool &none) {
+    if (!general) {
+        none = false;
+        return median_pair(t, false);
+    }
+    float pad = kInf;
+    bool all = true;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const bool drop = zj[j] == zc;
+        t[j] = drop ? pad : t[j];
+        pad = drop ? -pad : pad;
+        all = all && drop;
+    }
+    none = all;
+    return median_pair(t, pad < 0.f);  // odd number left out -> position 3
+}
+
+__device__ __forceinline__ float mean8(const float (&t)[8], const float (&zj)[8], float zc,
+                                       bool general, bool &none) {
+    if (!general) {
+        none = false;
+        const float s = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
+        return s * 0.125f;
+    }
+    float sum = 0.f;
+    int m = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const bool drop = zj[j] == zc;
+        sum += drop ? 0.f : t[j];
+        m += drop ? 0 : 1;
+    }
+    none = (m == 0);
+    return sum * rcp((float)m);
+}
+
+// Output row r of a tile from the window (prev, cur, next); `pend` holds the
+// raw loads of row r + 1 on entry and those of row r + 2 on exit.
+template <int KIND, bool FD, int AGG, int OUT, int PX>
+__device__ __forceinline__ void tile_row(const FrameDesc &f, const InBuf &ib, int r, int col,
+                                         int col_off, int halo_off, float wa, float wb,
+                                         RawRow<KIND, PX> &pend, const RowState<PX> &prev,
+                                         RowState<PX> &cur, RowState<PX> &next) {
+    finish_row<KIND, PX>(pend, next.row);
+    load_raw<KIND, PX>(ib, r + 2, col_off, halo_off, pend);  // prefetch
+    make_pairs<PX>(cur.row, next.row, cur.below);
+    const Row<PX> &rp = prev.row, &rc = cur.row, &rn = next.row;
+    const Pairs<PX> &pu = prev.below, &pd = cur.below;
+
+    // vertical central differences of s at columns -1..PX
+    float V[PX + 2];
+#pragma unroll
+    for (int i = 0; i < PX + 2; ++i) {
+        if constexpr (FD) {
+            if (i == 0 || i == PX + 1) { V[i] = 0.f; continue; }
+        }
+        if constexpr (KIND == KIND_DISP)
+            V[i] = rn.z[i] - rp.z[i];
+        else
+            V[i] = (rp.z[i] - rn.z[i]) * (rp.s[i] * rn.s[i]);
+    }
+
+    using OT = typename Out<OUT>::T;
+    Vec<OT, PX> ox, oy, oz;
+    uint8_t mk[PX];
+    const float fv = (float)r - f.v0;
+#pragma unroll
+    for (int k = 0; k < PX; ++k) {
+        const int c = k + 1;
+        const float zc = rc.z[c];
+        const bool valid = fminf(fminf(rp.hmin[k], rc.hmin[k]), rn.hmin[k]) > 0.f;
+        float Gu, Gv;
+        if constexpr (FD) {
+            Gu = rc.D[k];
+            Gv = V[c];
+        } else {
+            Gu = fmaf(wa, rp.D[k] + rn.D[k], wb * rc.D[k]);
+            Gv = fmaf(wa, V[c - 1] + V[c + 1], wb * V[c]);
+        }
+        const float fu = (float)(col + k) - f.u0;
+        const float B = fmaf(fu, Gu, fv * Gv);
+        const float Spp = Gu + Gv, Spm = Gu - Gv;
+        // slots: E, W, S, N, SE, NW, SW, NE
+        const float zj[8] = {rc.z[c + 1], rc.z[c - 1], rn.z[c], rp.z[c],
+                             rn.z[c + 1], rp.z[c - 1], rn.z[c - 1], rp.z[c + 1]};
+        const float Nj[8] = {Gu, -Gu, Gv, -Gv, Spp, -Spp, -Spm, Spm};
+        const float rj[8] = {rc.rE[c], -rc.rE[c - 1], pd.rS[k], -pu.rS[k],
+                             pd.rSE[c], -pu.rSE[k], pd.rSW[k], -pu.rSW[c]};
+        float t[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if constexpr (KIND == KIND_DISP)
+                t[j] = -(Nj[j] * zc) * rj[j];
+            else
+                t[j] = fmaf(Nj[j] * zc, rj[j], Nj[j]);
+        }
+        // A slot is left out iff raw_j == raw, i.e. its pair reciprocal is
+        // +-inf.  That is rare in float data: pad only when a valid pixel of
+        // this wavefront needs it (the choice is wave-uniform, and both paths
+        // give the same result when nothing is left out).
+        const float rmax = fmaxf(fmaxf(fmaxf(fabsf(rj[0]), fabsf(rj[1])), fabsf(rj[2])),
+                                 fmaxf(fmaxf(fmaxf(fabsf(rj[3]), fabsf(rj[4])), fabsf(rj[5])),
+                                       fmaxf(fabsf(rj[6]), fabsf(rj[7]))));
+        const bool any_drop = !(rmax < kInf);
+        const bool general = __builtin_amdgcn_ballot_w64(valid && any_drop) != 0;
+        bool none;
+        const float phi = (AGG == AGG_MEAN) ? mean8(t, zj, zc, general, none)
+                                            : median8(t, zj, zc, general, none);
+        const float nx = f.fx * Gu, ny = f.fy * Gv, nz = B + phi;
+        const float n2 = fmaf(nx, nx, fmaf(ny, ny, nz * nz));
+        const bool deg = none || !(n2 > 0.f);
+        const float inv = __builtin_amdgcn_rsqf(n2);
+        const bool keep = valid && !deg;
+        ox.v[k] = Out<OUT>::cvt(keep ? -nx * inv : 0.f);
+        oy.v[k] = Out<OUT>::cvt(keep ? -ny * inv : 0.f);
+        oz.v[k] = Out<OUT>::cvt(keep ? nz * inv : (valid ? -1.f : 0.f));
+        mk[k] = valid ? 1 : 0;
+    }
+    if (col < f.W) {
+        OT *o = static_cast<OT *>(f.out) + (int64_t)r * f.out_pitch + col;
+        *reinterpret_cast<Vec<OT, PX> *>(o) = ox;
+        *reinterpret_cast<Vec<OT, PX> *>(o + f.out_plane) = oy;
+        *reinterpret_cast<Vec<OT, PX> *>(o + 2 * f.out_plane) = oz;
+        if (f.mask) {
+            typename MaskWord<PX>::T w = 0;
+#pragma unroll
+            for (int k = 0; k < PX; ++k) w |= (typename MaskWord<PX>::T)mk[k] << (8 * k);
+            *reinterpret_cast<typename MaskWord<PX>::T *>(f.mask + (int64_t)r * f.mask_pitch +
+                                                          col) = w;
+        }
+    }
+}
+
+// One tile: columns [c0, c0 + 64 PX) x rows [r0, r1) of frame f.  The row
+// loop is unrolled three times with the window's roles rotating, so no
+// register state is copied between rows.
 template <int KIND, bool FD, int AGG, int OUT, int PX>
 __device__ __forceinline__ void run_tile(const FrameDesc &f, int c0, int r0, int r1, float wa,
                                          float wb) {
+    using T = typename Raw<KIND>::T;
     const int lane = threadIdx.x & (kWave - 1);
     const int col = c0 + lane * PX;
-    const bool halo_lane = (lane == 0) | (lane == kWave - 1);
-    const int hcol = (lane == 0) ? c0 - 1 : c0 + kWave * PX;
-    const float fu0 = f.u0, fv0 = f.v0;
+    const int esz = (int)sizeof(T);
+    const InBuf ib = make_inbuf(f.in, f.in_pitch, f.H, esz);
+    const int col_off = col < f.W ? col * esz : kOOB;
+    int hcol = -1;
+    if (lane == 0) hcol = c0 - 1;
+    if (lane == kWave - 1) hcol = c0 + kWave * PX;
+    const int halo_off = (hcol >= 0 && hcol < f.W) ? hcol * esz : kOOB;
 
     RawRow<KIND, PX> pend;
-    Row<PX> rp, rc, rn;
-    Pairs<PX> pu, pd;
-    load_raw<KIND, PX>(f, r0 - 1, col, hcol, halo_lane, pend);
-    finish_row<KIND, PX>(pend, rp);
-    load_raw<KIND, PX>(f, r0, col, hcol, halo_lane, pend);
-    finish_row<KIND, PX>(pend, rc);
-    make_pairs<PX>(rp, rc, pu);
-    load_raw<KIND, PX>(f, r0 + 1, col, hcol, halo_lane, pend);
+    RowState<PX> A, B, C;
+    load_raw<KIND, PX>(ib, r0 - 1, col_off, halo_off, pend);
+    finish_row<KIND, PX>(pend, A.row);
+    load_raw<KIND, PX>(ib, r0, col_off, halo_off, pend);
+    finish_row<KIND, PX>(pend, B.row);
+    make_pairs<PX>(A.row, B.row, A.below);
+    load_raw<KIND, PX>(ib, r0 + 1, col_off, halo_off, pend);
 
-    using OT = typename Out<OUT>::T;
-    OT *out0 = static_cast<OT *>(f.out);
-
-    for (int r = r0; r < r1; ++r) {
-        finish_row<KIND, PX>(pend, rn);
-        load_raw<KIND, PX>(f, r + 2, col, hcol, halo_lane, pend);  // prefetch
-        make_pairs<PX>(rc, rn, pd);
-
-        // vertical central differences of s at columns -1..PX
-        float V[PX + 2];
-#pragma unroll
-        for (int i = 0; i < PX + 2; ++i) {
-            if constexpr (FD) {
-                if (i == 0 || i == PX + 1) { V[i] = 0.f; continue; }
-            }
-            if constexpr (KIND == KIND_DISP)
-                V[i] = rn.z[i] - rp.z[i];
-            else
-                V[i] = (rp.z[i] - rn.z[i]) * (rp.s[i] * rn.s[i]);
-        }
-
-        Vec<OT, PX> ox, oy, oz;
-        uint8_t mk[PX];
-        const float fv = (float)r - fv0;
-#pragma unroll
-        for (int k = 0; k < PX; ++k) {
-            const int c = k + 1;
-            const float zc = rc.z[c];
-            const bool valid = fminf(fminf(rp.hmin[k], rc.hmin[k]), rn.hmin[k]) > 0.f;
-            float Gu, Gv;
-            if constexpr (FD) {
-                Gu = rc.D[k];
-                Gv = V[c];
-            } else {
-                Gu = fmaf(wa, rp.D[k] + rn.D[k], wb * rc.D[k]);
-                Gv = fmaf(wa, V[c - 1] + V[c + 1], wb * V[c]);
-            }
-            const float fu = (float)(col + k) - fu0;
-            const float B = fmaf(fu, Gu, fv * Gv);
-            const float Spp = Gu + Gv, Spm = Gu - Gv;
-            // slots: E, W, S, N, SE, NW, SW, NE
-            const float zj[8] = {rc.z[c + 1], rc.z[c - 1], rn.z[c], rp.z[c],
-                                 rn.z[c + 1], rp.z[c - 1], rn.z[c - 1], rp.z[c + 1]};
-            const float Nj[8] = {Gu, -Gu, Gv, -Gv, Spp, -Spp, -Spm, Spm};
-            const float rj[8] = {rc.rE[c], -rc.rE[c - 1], pd.rS[k], -pu.rS[k],
-                                 pd.rSE[c], -pu.rSE[k], pd.rSW[k], -pu.rSW[c]};
-            float t[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                if constexpr (KIND == KIND_DISP)
-                    t[j] = -(Nj[j] * zc) * rj[j];
-                else
-                    t[j] = fmaf(Nj[j] * zc, rj[j], Nj[j]);
-            }
-            float phi;
-            bool none;
-            if constexpr (AGG == AGG_MEAN) {
-                float sum = 0.f;
-                int m = 0;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const bool keep = zj[j] != zc;
-                    sum += keep ? t[j] : 0.f;
-                    m += keep ? 1 : 0;
-                }
-                none = (m == 0);
-                phi = sum * rcp((float)m);
-            } else {
-                float pad = kInf;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const bool drop = zj[j] == zc;
-                    t[j] = drop ? pad : t[j];
-                    pad = drop ? -pad : pad;
-                }
-                none = true;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) none = none && (zj[j] == zc);
-                sort4(t[0], t[1], t[2], t[3]);
-                sort4(t[4], t[5], t[6], t[7]);
-                // merged order statistics 3 and 4 (0-based) of two sorted quads
-                const float x3 = fminf(fminf(fminf(t[7], fmaxf(t[0], t[6])),
-                                             fminf(fmaxf(t[1], t[5]), fmaxf(t[2], t[4]))),
-                                       t[3]);
-                const float x4 = fminf(fminf(fmaxf(t[0], t[7]), fmaxf(t[1], t[6])),
-                                       fminf(fmaxf(t[2], t[5]), fmaxf(t[3], t[4])));
-                const bool odd = pad < 0.f;  // an odd number of slots left out
-                phi = odd ? x3 : 0.5f * (x3 + x4);
-            }
-            const float nx = f.fx * Gu, ny = f.fy * Gv, nz = B + phi;
-            const float n2 = fmaf(nx, nx, fmaf(ny, ny, nz * nz));
-            const bool deg = none || !(n2 > 0.f);
-            const float inv = __builtin_amdgcn_rsqf(n2);
-            float ox_ = -nx * inv, oy_ = -ny * inv, oz_ = nz * inv;
-            ox_ = deg ? 0.f : ox_;
-            oy_ = deg ? 0.f : oy_;
-            oz_ = deg ? -1.f : oz_;
-            ox.v[k] = Out<OUT>::cvt(valid ? ox_ : 0.f);
-            oy.v[k] = Out<OUT>::cvt(valid ? oy_ : 0.f);
-            oz.v[k] = Out<OUT>::cvt(valid ? oz_ : 0.f);
-            mk[k] = valid ? 1 : 0;
-        }
-        if (col < f.W) {
-            OT *o = out0 + (int64_t)r * f.out_pitch + col;
-            *reinterpret_cast<Vec<OT, PX> *>(o) = ox;
-            *reinterpret_cast<Vec<OT, PX> *>(o + f.out_plane) = oy;
-            *reinterpret_cast<Vec<OT, PX> *>(o + 2 * f.out_plane) = oz;
-            if (f.mask) {
-                typename MaskWord<PX>::T w = 0;
-#pragma unroll
-                for (int k = 0; k < PX; ++k) w |= (typename MaskWord<PX>::T)mk[k] << (8 * k);
-                *reinterpret_cast<typename MaskWord<PX>::T *>(f.mask + (int64_t)r * f.mask_pitch +
-                                                              col) = w;
-            }
-        }
-        rp = rc;
-        rc = rn;
-        pu = pd;
+    for (int r = r0; r < r1; r += 3) {
+        tile_row<KIND, FD, AGG, OUT, PX>(f, ib, r, col, col_off, halo_off, wa, wb, pend, A, B, C);
+        if (r + 1 >= r1) break;
+        tile_row<KIND, FD, AGG, OUT, PX>(f, ib, r + 1, col, col_off, halo_off, wa, wb, pend, B, C, A);
+        if (r + 2 >= r1) break;
+        tile_row<KIND, FD, AGG, OUT, PX>(f, ib, r + 2, col, col_off, halo_off, wa, wb, pend, C, A, B);
     }
 }
 
@@ -340,8 +428,10 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 template <int KIND, bool FD, int AGG, int OUT, int PX>
 __global__ __launch_bounds__(kBlock) void sne_uniform_kernel(UniformArgs a) {
     const int b = a.xcd_remap ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    const int tile = b * kWavesPerBlock + (int)(threadIdx.x >> 6);
-    if (tile >= a.ntiles) return;  // uniform per wavefront
+    // wave-uniform by construction; readfirstlane lets the compiler keep the
+    // frame's buffer resource in scalar registers
+    const int tile = __builtin_amdgcn_readfirstlane(b * kWavesPerBlock + (int)(threadIdx.x >> 6));
+    if (tile >= a.ntiles) return;
     const int per_frame = a.nbands * a.nstrips;
     const int frame = tile / per_frame;
     const int rem = tile - frame * per_frame;
@@ -363,15 +453,17 @@ __global__ __launch_bounds__(kBlock) void sne_uniform_kernel(UniformArgs a) {
 template <int KIND, bool FD, int AGG, int OUT, int PX>
 __global__ __launch_bounds__(kBlock) void sne_batch_kernel(BatchArgs a) {
     const int lane = threadIdx.x & (kWave - 1);
+    const int nframes = a.counts ? a.counts[0] : a.nframes;
+    const int ntiles = a.counts ? a.counts[1] : a.ntiles;
     for (;;) {
         int base = 0;
         if (lane == 0) base = atomicAdd(a.counter, a.chunk);
         base = __builtin_amdgcn_readfirstlane(base);  // lane 0 is the first active lane
-        if (base >= a.ntiles) return;
-        const int end = min(base + a.chunk, a.ntiles);
+        if (base >= ntiles) return;
+        const int end = min(base + a.chunk, ntiles);
         for (int tile = base; tile < end; ++tile) {
             // frame = last index with tile_start[frame] <= tile
-            int lo = 0, hi = a.nframes - 1;
+            int lo = 0, hi = nframes - 1;
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
                 if (a.tile_start[mid] <= tile) lo = mid; else hi = mid - 1;

@@ -1,0 +1,587 @@
+// sne_server.hip - continuous-batching serving loop of libsne.
+//
+// Frames from many sensor streams are submitted as requests; a scheduler
+// thread admits them against an HBM budget (the output arena), groups
+// whatever is admitted into a batch whenever one of `max_inflight` slots is
+// free, and launches the batch as ONE persistent uneven-batch kernel on that
+// slot's stream.  Batches on different slots run concurrently on the GPU;
+// requests that arrive meanwhile go into the next batch.  Each slot owns its
+// pinned descriptor staging, its device tables and (optionally) a captured
+// hipGraph per columns-per-lane class: {staging -> device copy, counter
+// reset, persistent kernel}; a batch rewrites the staging and replays the
+// graph.  Scheduling policy lives in sne_sched.cpp (pure C++).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <random>
+#include <thread>
+#include <vector>
+
+#include "sne_host.h"
+#include "sne_sched.h"
+
+namespace sne {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Header {
+    int32_t nframes, ntiles;
+    int32_t pad[62];
+};
+
+struct SlotRes {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    void *h_stage = nullptr;   // pinned: Header | FrameDesc[cap] | start[cap+1] | nstrips[cap]
+    void *d_stage = nullptr;   // device mirror
+    int32_t *d_counter = nullptr;
+    size_t bytes = 0;
+    hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};  // px = 1, 2, 4
+    const void *graph_ktable = nullptr;
+    bool launched = false;
+    int rc = 0;
+};
+
+int px_index(int px) { return px == 4 ? 2 : (px == 2 ? 1 : 0); }
+
+struct Payload {
+    const void *in;
+    int64_t in_pitch;
+};
+
+class HipExecutor : public sched::Executor {
+public:
+    sne_ctx *ctx = nullptr;
+    sne_server_config cfg{};
+    uint8_t *arena = nullptr;
+    std::vector<SlotRes> slots;
+    size_t cap = 0;
+    int rows = 16;
+
+    size_t off_frames() const { return sizeof(Header); }
+    size_t off_start() const { return off_frames() + cap * sizeof(FrameDesc); }
+    size_t off_ns() const { return off_start() + (cap + 1) * sizeof(int32_t); }
+
+    int init(sne_ctx *c, const sne_server_config &conf, uint8_t *arena_base) {
+        ctx = c;
+        cfg = conf;
+        arena = arena_base;
+        cap = (size_t)cfg.max_batch_frames;
+        slots.resize(cfg.max_inflight);
+        const size_t bytes = off_ns() + cap * sizeof(int32_t);
+        for (auto &s : slots) {
+            s.bytes = bytes;
+            if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess ||
+                hipHostMalloc(&s.h_stage, bytes, hipHostMallocDefault) != hipSuccess ||
+                hipMalloc(&s.d_stage, bytes) != hipSuccess ||
+                hipMalloc(&s.d_counter, sizeof(int32_t)) != hipSuccess)
+                return SNE_ERR_HIP;
+            std::memset(s.h_stage, 0, bytes);
+        }
+        return SNE_OK;
+    }
+
+    void destroy() {
+        for (auto &s : slots) {
+            if (s.stream) (void)hipStreamSynchronize(s.stream);
+            for (auto &g : s.graph)
+                if (g) (void)hipGraphExecDestroy(g);
+            if (s.done) (void)hipEventDestroy(s.done);
+            if (s.stream) (void)hipStreamDestroy(s.stream);
+            if (s.h_stage) (void)hipHostFree(s.h_stage);
+            if (s.d_stage) (void)hipFree(s.d_stage);
+            if (s.d_counter) (void)hipFree(s.d_counter);
+        }
+        slots.clear();
+    }
+
+    BatchArgs args(SlotRes &s) const {
+        BatchArgs a;
+        uint8_t *d = (uint8_t *)s.d_stage;
+        a.frames = (const FrameDesc *)(d + off_frames());
+        a.tile_start = (const int32_t *)(d + off_start());
+        a.nstrips = (const int32_t *)(d + off_ns());
+        a.ktable = reinterpret_cast<const float4 *>(ctx->d_K);
+        a.counter = s.d_counter;
+        a.counts = (const int32_t *)d;  // Header.nframes, Header.ntiles
+        a.nframes = 0;
+        a.ntiles = 0;
+        a.rows = rows;
+        a.chunk = 1;
+        grad_weights(cfg.grad, a.wa, a.wb);
+        return a;
+    }
+
+    int grid() const {
+        const int occ = ctx->occ_blocks > 0 ? ctx->occ_blocks : 8;
+        return ctx->num_cu * occ;
+    }
+
+    // The steps of one batch, enqueued on the slot's stream.
+    hipError_t enqueue(SlotRes &s, int px) {
+        hipError_t e = hipMemcpyAsync(s.d_stage, s.h_stage, s.bytes, hipMemcpyHostToDevice,
+                                      s.stream);
+        if (e != hipSuccess) return e;
+        if ((e = launch_zero_counter(s.d_counter, s.stream)) != hipSuccess) return e;
+        Variant v{cfg.kind, cfg.grad, cfg.agg, cfg.out_type, px};
+        return launch_batch(v, args(s), grid(), s.stream);
+    }
+
+    int build_graph(SlotRes &s, int px) {
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ex = nullptr;
+        if (hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return SNE_ERR_HIP;
+        const hipError_t e = enqueue(s, px);
+        const hipError_t e2 = hipStreamEndCapture(s.stream, &g);
+        if (e != hipSuccess || e2 != hipSuccess || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            return SNE_ERR_HIP;
+        }
+        const hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e3 != hipSuccess) return SNE_ERR_HIP;
+        s.graph[px_index(px)] = ex;
+        return SNE_OK;
+    }
+
+    int launch(sched::Batch &b) override {
+        SlotRes &s = slots[b.slot];
+        Header *h = (Header *)s.h_stage;
+        FrameDesc *fd = (FrameDesc *)((uint8_t *)s.h_stage + off_frames());
+        int32_t *start = (int32_t *)((uint8_t *)s.h_stage + off_start());
+        int32_t *ns = (int32_t *)((uint8_t *)s.h_stage + off_ns());
+        const size_t oe = out_elem(cfg.out_type);
+        int px = 4;
+        for (auto *q : b.reqs) {
+            const Payload *p = (const Payload *)q->payload;
+            uint8_t *out = arena + q->out_offset;
+            uint8_t *mask = out + 3 * (size_t)q->H * q->W * oe;
+            px = std::min(px, max_px(p->in, out, mask, q->W, p->in_pitch, q->W, q->W, 0, 0, 0,
+                                     (int64_t)q->H * q->W, cfg.kind, cfg.out_type));
+        }
+        int64_t tiles = 0;
+        for (size_t i = 0; i < b.reqs.size(); ++i) {
+            auto *q = b.reqs[i];
+            const Payload *p = (const Payload *)q->payload;
+            uint8_t *out = arena + q->out_offset;
+            uint8_t *mask = out + 3 * (size_t)q->H * q->W * oe;
+            const sne_intrinsics unused{1.f, 1.f, 0.f, 0.f};  // the kernel reads the table
+            fd[i] = make_desc(p->in, out, mask, q->H, q->W, p->in_pitch, q->W, q->W, unused);
+            fd[i].k_index = q->stream;
+            const int nst = (q->W + 64 * px - 1) / (64 * px);
+            const int nb = (q->H + rows - 1) / rows;
+            start[i] = (int32_t)tiles;
+            ns[i] = nst;
+            tiles += (int64_t)nst * nb;
+        }
+        start[b.reqs.size()] = (int32_t)tiles;
+        h->nframes = (int32_t)b.reqs.size();
+        h->ntiles = (int32_t)tiles;
+        hipSetDevice(ctx->device);
+        hipError_t e;
+        if (cfg.use_graphs) {
+            if (s.graph_ktable != ctx->d_K) {  // the table moved: recapture
+                for (auto &g : s.graph)
+                    if (g) (void)hipGraphExecDestroy(g);
+                s.graph[0] = s.graph[1] = s.graph[2] = nullptr;
+                s.graph_ktable = ctx->d_K;
+            }
+            if (!s.graph[px_index(px)]) {
+                const int rc = build_graph(s, px);
+                if (rc != SNE_OK) return rc;
+            }
+            e = hipGraphLaunch(s.graph[px_index(px)], s.stream);
+        } else {
+            e = enqueue(s, px);
+        }
+        if (e != hipSuccess || hipEventRecord(s.done, s.stream) != hipSuccess) return SNE_ERR_HIP;
+        s.launched = true;
+        s.rc = 0;
+        return SNE_OK;
+    }
+
+    bool done(const sched::Batch &b) override {
+        SlotRes &s = slots[b.slot];
+        const hipError_t e = hipEventQuery(s.done);
+        if (e == hipErrorNotReady) return false;
+        s.rc = (e == hipSuccess) ? 0 : SNE_ERR_HIP;
+        return true;
+    }
+
+    int result(const sched::Batch &b) override { return slots[b.slot].rc; }
+};
+
+}  // namespace
+}  // namespace sne
+
+struct sne_server {
+    sne_ctx *ctx = nullptr;
+    sne_server_config cfg{};
+    uint8_t *arena = nullptr;
+    sne::HipExecutor ex;
+    sne::sched::Scheduler *sched = nullptr;
+    std::mutex mu;
+    std::thread worker;
+    std::atomic<bool> stop{false};
+    sne::Clock::time_point t0;
+    std::vector<sne::Payload *> payloads;  // freed at destroy (one per request)
+    std::mutex pay_mu;
+
+    double now() const {
+        return std::chrono::duration<double>(sne::Clock::now() - t0).count();
+    }
+};
+
+namespace sne {
+namespace {
+
+void worker_loop(sne_server *srv) {
+    hipSetDevice(srv->ctx->device);
+    while (!srv->stop.load(std::memory_order_relaxed)) {
+        bool busy;
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            srv->sched->step(srv->now());
+            busy = !srv->sched->idle();
+        }
+        if (busy)
+            std::this_thread::yield();
+        else
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+}
+
+bool valid_config(const sne_server_config &c) {
+    return valid_enum(c.kind, c.grad, c.agg, c.out_type) && c.max_inflight >= 1 &&
+           c.max_inflight <= 8 && c.max_batch_frames >= 1 && c.max_batch_frames <= 65536 &&
+           c.max_batch_pixels >= 1 && c.hbm_budget_bytes >= 4096 && c.queue_capacity >= 1 &&
+           c.reserved == 0;
+}
+
+uint64_t out_bytes(const sne_server_config &c, int H, int W) {
+    return (uint64_t)H * W * (3 * out_elem(c.out_type) + 1);
+}
+
+void fill_stats(const sched::Stats &st, uint64_t arena_free, sne_server_stats *o) {
+    std::memset(o, 0, sizeof *o);
+    o->submitted = st.submitted;
+    o->completed = st.completed;
+    o->failed = st.failed;
+    o->rejected_full = st.rejected_full;
+    o->rejected_budget = st.rejected_budget;
+    o->batches = st.batches;
+    o->mean_batch_frames = st.batches ? (double)st.frames_in_batches / st.batches : 0.0;
+    o->latency_p50 = sched::quantile(st.latencies, 0.50);
+    o->latency_p90 = sched::quantile(st.latencies, 0.90);
+    o->latency_p99 = sched::quantile(st.latencies, 0.99);
+    o->latency_p999 = sched::quantile(st.latencies, 0.999);
+    o->latency_max = sched::quantile(st.latencies, 1.0);
+    const double span = st.last_done - st.first_arrival;
+    if (span > 0) {
+        o->mpix_per_s = (double)st.pixels_done / span / 1e6;
+        o->frames_per_s = (double)st.completed / span;
+    }
+    o->arena_free_bytes = (int64_t)arena_free;
+}
+
+}  // namespace
+}  // namespace sne
+
+using namespace sne;
+
+extern "C" {
+
+int sne_server_create(sne_server **out, sne_ctx *ctx, const sne_server_config *cfg) {
+    if (!out) return SNE_ERR_ARG;
+    *out = nullptr;
+    if (!ctx || !cfg || !valid_config(*cfg)) return SNE_ERR_ARG;
+    hipSetDevice(ctx->device);
+    sne_server *s = new sne_server();
+    s->ctx = ctx;
+    s->cfg = *cfg;
+    if (hipMalloc(&s->arena, (size_t)cfg->hbm_budget_bytes) != hipSuccess) {
+        delete s;
+        return SNE_ERR_HIP;
+    }
+    if (s->ex.init(ctx, *cfg, s->arena) != SNE_OK) {
+        s->ex.destroy();
+        (void)hipFree(s->arena);
+        delete s;
+        return SNE_ERR_HIP;
+    }
+    Variant v{cfg->kind, cfg->grad, cfg->agg, cfg->out_type, 4};
+    s->ex.rows = pick_tile(ctx, 1080, 1920, cfg->max_batch_frames, v, 4).rows;
+    sched::Config sc;
+    sc.max_inflight = cfg->max_inflight;
+    sc.max_batch_frames = cfg->max_batch_frames;
+    sc.max_batch_pixels = (uint64_t)cfg->max_batch_pixels;
+    sc.budget_bytes = (uint64_t)cfg->hbm_budget_bytes;
+    sc.align = 256;
+    sc.queue_capacity = (size_t)cfg->queue_capacity;
+    s->sched = new sched::Scheduler(sc, &s->ex);
+    s->t0 = Clock::now();
+    s->worker = std::thread(worker_loop, s);
+    *out = s;
+    return SNE_OK;
+}
+
+double sne_server_now(const sne_server *srv) { return srv ? srv->now() : 0.0; }
+
+int sne_server_submit(sne_server *srv, const sne_request *req, uint64_t *ticket) {
+    if (!srv || !req || !req->in || req->H < 1 || req->W < 1 || req->in_pitch < req->W ||
+        req->reserved != 0)
+        return SNE_ERR_ARG;
+    if (req->stream_id < 0 || req->stream_id >= srv->ctx->nK) return SNE_ERR_ARG;
+    if ((int64_t)(req->H + 2) * req->in_pitch * (int64_t)in_elem(srv->cfg.kind) >= INT32_MAX)
+        return SNE_ERR_UNSUPPORTED;
+    Payload *p = new Payload{req->in, req->in_pitch};
+    sched::Request r;
+    r.stream = req->stream_id;
+    r.H = req->H;
+    r.W = req->W;
+    r.out_bytes = out_bytes(srv->cfg, req->H, req->W);
+    r.payload = p;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    r.t_arrival = req->t_arrival >= 0 ? req->t_arrival : srv->now();
+    const int rc = srv->sched->submit(r, ticket);
+    if (rc != 0) {
+        delete p;
+        return rc == -3 ? SNE_ERR_BUDGET : SNE_ERR_FULL;
+    }
+    {
+        std::lock_guard<std::mutex> pk(srv->pay_mu);
+        srv->payloads.push_back(p);
+    }
+    return SNE_OK;
+}
+
+int sne_server_poll(sne_server *srv, sne_completion *out, int32_t max, int32_t *n) {
+    if (!srv || !n || max < 0 || (max > 0 && !out)) return SNE_ERR_ARG;
+    std::vector<sched::Request> done;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        done = srv->sched->take_completed((size_t)max);
+    }
+    const size_t oe = out_elem(srv->cfg.out_type);
+    for (size_t i = 0; i < done.size(); ++i) {
+        const sched::Request &q = done[i];
+        sne_completion &c = out[i];
+        c.ticket = q.ticket;
+        c.status = q.status;
+        c.stream_id = q.stream;
+        c.H = q.H;
+        c.W = q.W;
+        c.normals = srv->arena + q.out_offset;
+        c.mask = srv->arena + q.out_offset + 3 * (size_t)q.H * q.W * oe;
+        c.t_arrival = q.t_arrival;
+        c.t_launch = q.t_launch;
+        c.t_done = q.t_done;
+    }
+    *n = (int32_t)done.size();
+    return SNE_OK;
+}
+
+int sne_server_release(sne_server *srv, uint64_t ticket) {
+    if (!srv) return SNE_ERR_ARG;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    const int rc = srv->sched->release(ticket);
+    return rc == 0 ? SNE_OK : (rc == -5 ? SNE_ERR_STATE : SNE_ERR_ARG);
+}
+
+int sne_server_drain(sne_server *srv, double timeout_s) {
+    if (!srv) return SNE_ERR_ARG;
+    const double t_end = srv->now() + timeout_s;
+    for (;;) {
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            if (srv->sched->idle()) return SNE_OK;
+        }
+        if (srv->now() > t_end) return SNE_ERR_STATE;
+        std::this_thread::sleep_for(std::chrono::microseconds(50));
+    }
+}
+
+int sne_server_get_stats(sne_server *srv, sne_server_stats *st) {
+    if (!srv || !st) return SNE_ERR_ARG;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    fill_stats(srv->sched->stats(), srv->sched->arena_free(), st);
+    return SNE_OK;
+}
+
+int sne_server_reset_stats(sne_server *srv) {
+    if (!srv) return SNE_ERR_ARG;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->sched->reset_stats();
+    return SNE_OK;
+}
+
+int sne_server_destroy(sne_server *srv) {
+    if (!srv) return SNE_OK;
+    (void)sne_server_drain(srv, 30.0);
+    srv->stop = true;
+    if (srv->worker.joinable()) srv->worker.join();
+    srv->ex.destroy();
+    delete srv->sched;
+    if (srv->arena) (void)hipFree(srv->arena);
+    for (auto *p : srv->payloads) delete p;
+    delete srv;
+    return SNE_OK;
+}
+
+int sne_server_run_open_loop(sne_server *srv, const sne_loadgen_config *cfg,
+                             sne_server_stats *st) {
+    if (!srv || !cfg || !st || cfg->n_streams < 1 || cfg->n_streams > srv->ctx->nK ||
+        !(cfg->total_rate > 0) || !(cfg->duration_s > 0) || cfg->ring < 1 || !cfg->frames ||
+        !cfg->H || !cfg->W || !cfg->pitch || cfg->n_producers < 1 || cfg->n_producers > 256)
+        return SNE_ERR_ARG;
+    // arrival schedule: independent Poisson processes, one per stream
+    struct Arr {
+        double t;
+        int32_t stream, k;
+    };
+    std::vector<std::vector<Arr>> per_prod(cfg->n_producers);
+    const double rate = cfg->total_rate / cfg->n_streams;
+    for (int s = 0; s < cfg->n_streams; ++s) {
+        std::mt19937_64 g(cfg->seed * 1000003ull + (uint64_t)s);
+        std::exponential_distribution<double> ex(rate);
+        double t = ex(g);
+        int k = 0;
+        while (t < cfg->duration_s) {
+            per_prod[s % cfg->n_producers].push_back(Arr{t, s, k++});
+            t += ex(g);
+        }
+    }
+    uint64_t total = 0;
+    for (auto &v : per_prod) {
+        std::sort(v.begin(), v.end(), [](const Arr &a, const Arr &b) { return a.t < b.t; });
+        total += v.size();
+    }
+    (void)sne_server_reset_stats(srv);
+    const double base = srv->now() + 0.01;
+    std::atomic<uint64_t> submitted{0}, refused{0};
+    std::vector<std::thread> prods;
+    for (int p = 0; p < cfg->n_producers; ++p) {
+        prods.emplace_back([&, p]() {
+            for (const Arr &a : per_prod[p]) {
+                const double when = base + a.t;
+                for (;;) {
+                    const double d = when - srv->now();
+                    if (d <= 0) break;
+                    if (d > 200e-6)
+                        std::this_thread::sleep_for(std::chrono::microseconds((int)(d * 1e6) - 100));
+                    else
+                        std::this_thread::yield();
+                }
+                sne_request r;
+                r.in = cfg->frames[(size_t)a.stream * cfg->ring + (a.k % cfg->ring)];
+                r.H = cfg->H[a.stream];
+                r.W = cfg->W[a.stream];
+                r.in_pitch = cfg->pitch[a.stream];
+                r.stream_id = a.stream;
+                r.reserved = 0;
+                r.t_arrival = when;  // latency counts from the scheduled arrival
+                uint64_t t;
+                if (sne_server_submit(srv, &r, &t) == SNE_OK)
+                    submitted++;
+                else
+                    refused++;
+            }
+        });
+    }
+    // the client: take results as they complete and hand the memory back
+    std::vector<sne_completion> buf(4096);
+    uint64_t finished = 0;
+    const double deadline = base + cfg->duration_s + 30.0;
+    int rc = SNE_OK;
+    for (;;) {
+        int32_t n = 0;
+        sne_server_poll(srv, buf.data(), (int32_t)buf.size(), &n);
+        for (int i = 0; i < n; ++i) {
+            if (buf[i].status != 0) rc = SNE_ERR_HIP;
+            sne_server_release(srv, buf[i].ticket);
+        }
+        finished += n;
+        if (finished + refused.load() >= total) break;
+        if (srv->now() > deadline) {
+            rc = SNE_ERR_STATE;
+            break;
+        }
+        if (n == 0) std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+    for (auto &t : prods) t.join();
+    sne_server_get_stats(srv, st);
+    return rc;
+}
+
+// Capacity simulator: the scheduler against a model of the GPU (a batch takes
+// overhead + pixels / rate seconds) on a simulated clock.
+int sne_sched_simulate(const sne_sim_config *cfg, sne_server_stats *st) {
+    if (!cfg || !st || cfg->n_streams < 1 || !(cfg->total_rate > 0) || !(cfg->duration_s > 0) ||
+        !(cfg->gpu_pixels_per_s > 0) || cfg->batch_overhead_s < 0 || !cfg->H || !cfg->W ||
+        cfg->max_inflight < 1 || cfg->max_inflight > 8 || cfg->max_batch_frames < 1 ||
+        cfg->budget_bytes < 4096)
+        return SNE_ERR_ARG;
+    struct SimExec : sched::Executor {
+        double now = 0, overhead = 0, rate = 1;
+        std::vector<double> end;
+        double gpu_free = 0;
+        int launch(sched::Batch &b) override {
+            // one GPU: batch work is processed in launch order at `rate`
+            // pixels/s; the launch overhead overlaps with a busy GPU
+            gpu_free = std::max(now + overhead, gpu_free) + (double)b.pixels / rate;
+            end[b.slot] = gpu_free;
+            return 0;
+        }
+        bool done(const sched::Batch &b) override { return now >= end[b.slot]; }
+    } ex;
+    ex.overhead = cfg->batch_overhead_s;
+    ex.rate = cfg->gpu_pixels_per_s;
+    ex.end.assign(cfg->max_inflight, 0.0);
+    sched::Config sc;
+    sc.max_inflight = cfg->max_inflight;
+    sc.max_batch_frames = cfg->max_batch_frames;
+    sc.max_batch_pixels = cfg->max_batch_pixels > 0 ? (uint64_t)cfg->max_batch_pixels : ~0ull;
+    sc.budget_bytes = (uint64_t)cfg->budget_bytes;
+    sched::Scheduler s(sc, &ex);
+    struct Arr {
+        double t;
+        int32_t stream;
+    };
+    std::vector<Arr> arr;
+    const double rate = cfg->total_rate / cfg->n_streams;
+    for (int k = 0; k < cfg->n_streams; ++k) {
+        std::mt19937_64 g(cfg->seed * 1000003ull + (uint64_t)k);
+        std::exponential_distribution<double> e(rate);
+        for (double t = e(g); t < cfg->duration_s; t += e(g)) arr.push_back(Arr{t, k});
+    }
+    std::sort(arr.begin(), arr.end(), [](const Arr &a, const Arr &b) { return a.t < b.t; });
+    const double dt = cfg->tick_s > 0 ? cfg->tick_s : 10e-6;
+    size_t i = 0;
+    for (double t = 0; (i < arr.size() || !s.idle()) && t < cfg->duration_s * 10 + 10; t += dt) {
+        ex.now = t;
+        while (i < arr.size() && arr[i].t <= t) {
+            sched::Request r;
+            r.stream = arr[i].stream;
+            r.H = cfg->H[r.stream];
+            r.W = cfg->W[r.stream];
+            r.out_bytes = (uint64_t)r.H * r.W * 7;  // fp16 normals + mask
+            r.t_arrival = arr[i].t;
+            s.submit(r, nullptr);
+            ++i;
+        }
+        s.step(t);
+        for (auto &q : s.take_completed(1 << 20)) s.release(q.ticket);
+    }
+    fill_stats(s.stats(), s.arena_free(), st);
+    return SNE_OK;
+}
+
+}  // extern "C"
