@@ -55,6 +55,61 @@ class Tile(ctypes.Structure):
     _fields_ = [("cols_per_lane", ctypes.c_int32), ("rows", ctypes.c_int32)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("grad", ctypes.c_int32), ("agg", ctypes.c_int32),
+                ("out_type", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
+                ("max_batch_frames", ctypes.c_int32), ("max_batch_pixels", ctypes.c_int64),
+                ("hbm_budget_bytes", ctypes.c_int64), ("queue_capacity", ctypes.c_int64),
+                ("use_graphs", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("input", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("in_pitch", ctypes.c_int64), ("stream_id", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("t_arrival", ctypes.c_double)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("stream_id", ctypes.c_int32), ("normals", ctypes.c_void_p),
+                ("mask", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("t_arrival", ctypes.c_double), ("t_launch", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("rejected_full", ctypes.c_uint64),
+                ("rejected_budget", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("mean_batch_frames", ctypes.c_double), ("latency_p50", ctypes.c_double),
+                ("latency_p90", ctypes.c_double), ("latency_p99", ctypes.c_double),
+                ("latency_p999", ctypes.c_double), ("latency_max", ctypes.c_double),
+                ("mpix_per_s", ctypes.c_double), ("frames_per_s", ctypes.c_double),
+                ("arena_free_bytes", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class LoadgenConfig(ctypes.Structure):
+    _fields_ = [("n_streams", ctypes.c_int32), ("n_producers", ctypes.c_int32),
+                ("total_rate", ctypes.c_double), ("duration_s", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("frames", ctypes.POINTER(ctypes.c_void_p)),
+                ("ring", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("H", ctypes.POINTER(ctypes.c_int32)), ("W", ctypes.POINTER(ctypes.c_int32)),
+                ("pitch", ctypes.POINTER(ctypes.c_int64))]
+
+
+class SimConfig(ctypes.Structure):
+    _fields_ = [("n_streams", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
+                ("max_batch_frames", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_batch_pixels", ctypes.c_int64), ("budget_bytes", ctypes.c_int64),
+                ("total_rate", ctypes.c_double), ("duration_s", ctypes.c_double),
+                ("gpu_pixels_per_s", ctypes.c_double), ("batch_overhead_s", ctypes.c_double),
+                ("tick_s", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("H", ctypes.POINTER(ctypes.c_int32)), ("W", ctypes.POINTER(ctypes.c_int32))]
+
+
 _lib = None
 _vp, _i32, _i64, _int = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int
 
@@ -76,6 +131,18 @@ _SIGS = {
     "sne_autotune": ([_vp, _i32, _i32, _i32, _int, _int, _int, _int, ctypes.POINTER(Tile)], _int),
     "sne_autotune_save": ([_vp, ctypes.c_char_p], _int),
     "sne_autotune_load": ([_vp, ctypes.c_char_p], _int),
+    "sne_server_create": ([ctypes.POINTER(_vp), _vp, ctypes.POINTER(ServerConfig)], _int),
+    "sne_server_submit": ([_vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)], _int),
+    "sne_server_poll": ([_vp, ctypes.POINTER(Completion), _i32, ctypes.POINTER(_i32)], _int),
+    "sne_server_release": ([_vp, ctypes.c_uint64], _int),
+    "sne_server_drain": ([_vp, ctypes.c_double], _int),
+    "sne_server_get_stats": ([_vp, ctypes.POINTER(ServerStats)], _int),
+    "sne_server_reset_stats": ([_vp], _int),
+    "sne_server_now": ([_vp], ctypes.c_double),
+    "sne_server_destroy": ([_vp], _int),
+    "sne_server_run_open_loop": ([_vp, ctypes.POINTER(LoadgenConfig), ctypes.POINTER(ServerStats)],
+                                 _int),
+    "sne_sched_simulate": ([ctypes.POINTER(SimConfig), ctypes.POINTER(ServerStats)], _int),
 }
 
 
@@ -230,6 +297,150 @@ class Context:
               lib().sne_estimate_batched(self._h, descs, n, kind_i, _enum(GRAD, grad, "grad"),
                                          _enum(AGG, agg, "agg"), out_i, _stream(stream)))
         return normals, masks
+
+
+class Server:
+    """sne_server_*: continuous-batching serving loop on a Context."""
+
+    def __init__(self, ctx: Context, kind="depth_u16", grad="fd", agg="mean", out="f16",
+                 max_inflight=3, max_batch_frames=256, max_batch_pixels=64 << 20,
+                 hbm_budget_bytes=4 << 30, queue_capacity=65536, use_graphs=True):
+        self.ctx = ctx
+        self.kind, self.out = _enum(KIND, kind, "kind"), _enum(OUT, out, "out")
+        cfg = ServerConfig(self.kind, _enum(GRAD, grad, "grad"), _enum(AGG, agg, "agg"),
+                           self.out, max_inflight, max_batch_frames, max_batch_pixels,
+                           hbm_budget_bytes, queue_capacity, 1 if use_graphs else 0, 0)
+        self._h = ctypes.c_void_p()
+        check("sne_server_create",
+              lib().sne_server_create(ctypes.byref(self._h), ctx.handle, ctypes.byref(cfg)))
+        self._keep = {}   # ticket -> input tensor kept alive until completion
+
+    def submit(self, frame: torch.Tensor, stream_id: int, t_arrival: float = -1.0) -> int:
+        if frame.dtype != KIND_DTYPE[self.kind]:
+            raise TypeError("server kind needs %s frames" % KIND_DTYPE[self.kind])
+        H, W = frame.shape
+        r = Request(frame.data_ptr(), H, W, _row_pitch(frame), int(stream_id), 0, float(t_arrival))
+        t = ctypes.c_uint64()
+        check("sne_server_submit", lib().sne_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
+        self._keep[t.value] = frame
+        return t.value
+
+    def poll(self, max_n: int = 1024):
+        buf = (Completion * max_n)()
+        n = ctypes.c_int32()
+        check("sne_server_poll", lib().sne_server_poll(self._h, buf, max_n, ctypes.byref(n)))
+        return [buf[i] for i in range(n.value)]
+
+    def result(self, c: Completion, copy: bool = True):
+        """(normals [3,H,W], mask [H,W]) of a completion, copied out of the
+        arena (the arena slot is still held until release)."""
+        dt = OUT_DTYPE[self.out]
+        esz = torch.tensor([], dtype=dt).element_size()
+        n = torch.empty((3, c.H, c.W), dtype=dt, device="cuda")
+        m = torch.empty((c.H, c.W), dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        _memcpy_d2d(n.data_ptr(), c.normals, 3 * c.H * c.W * esz)
+        _memcpy_d2d(m.data_ptr(), c.mask, c.H * c.W)
+        return n, m
+
+    def release(self, ticket: int):
+        check("sne_server_release", lib().sne_server_release(self._h, int(ticket)))
+        self._keep.pop(int(ticket), None)
+
+    def drain(self, timeout_s: float = 30.0):
+        check("sne_server_drain", lib().sne_server_drain(self._h, float(timeout_s)))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        check("sne_server_get_stats", lib().sne_server_get_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def reset_stats(self):
+        check("sne_server_reset_stats", lib().sne_server_reset_stats(self._h))
+
+    def now(self) -> float:
+        return lib().sne_server_now(self._h)
+
+    def run_open_loop(self, frames: Sequence[Sequence[torch.Tensor]], total_rate: float,
+                      duration_s: float, seed: int = 5000, n_producers: int = 8) -> dict:
+        """frames[s][k]: the device ring of stream s (stream s uses intrinsics
+        row s).  Returns the run's statistics."""
+        ns = len(frames)
+        ring = len(frames[0])
+        ptrs = (ctypes.c_void_p * (ns * ring))()
+        Hs = (ctypes.c_int32 * ns)()
+        Ws = (ctypes.c_int32 * ns)()
+        Ps = (ctypes.c_int64 * ns)()
+        for s_, fs in enumerate(frames):
+            if len(fs) != ring:
+                raise ValueError("every stream needs the same ring length")
+            Hs[s_], Ws[s_] = fs[0].shape
+            Ps[s_] = _row_pitch(fs[0])
+            for k, f in enumerate(fs):
+                if tuple(f.shape) != (Hs[s_], Ws[s_]) or f.dtype != KIND_DTYPE[self.kind]:
+                    raise ValueError("stream %d: frames differ in shape or dtype" % s_)
+                ptrs[s_ * ring + k] = f.data_ptr()
+        cfg = LoadgenConfig(ns, n_producers, float(total_rate), float(duration_s), int(seed),
+                            ctypes.cast(ptrs, ctypes.POINTER(ctypes.c_void_p)), ring, 0,
+                            ctypes.cast(Hs, ctypes.POINTER(ctypes.c_int32)),
+                            ctypes.cast(Ws, ctypes.POINTER(ctypes.c_int32)),
+                            ctypes.cast(Ps, ctypes.POINTER(ctypes.c_int64)))
+        st = ServerStats()
+        check("sne_server_run_open_loop",
+              lib().sne_server_run_open_loop(self._h, ctypes.byref(cfg), ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if self._h:
+            lib().sne_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def simulate(stream_shapes: Sequence[Tuple[int, int]], total_rate: float, duration_s: float,
+             gpu_pixels_per_s: float, batch_overhead_s: float = 20e-6, max_inflight: int = 3,
+             max_batch_frames: int = 256, max_batch_pixels: int = 0,
+             budget_bytes: int = 4 << 30, tick_s: float = 10e-6, seed: int = 5000) -> dict:
+    """sne_sched_simulate: the scheduler against a GPU model (host only)."""
+    ns = len(stream_shapes)
+    Hs = (ctypes.c_int32 * ns)(*[h for h, _ in stream_shapes])
+    Ws = (ctypes.c_int32 * ns)(*[w for _, w in stream_shapes])
+    cfg = SimConfig(ns, max_inflight, max_batch_frames, 0, max_batch_pixels, budget_bytes,
+                    float(total_rate), float(duration_s), float(gpu_pixels_per_s),
+                    float(batch_overhead_s), float(tick_s), int(seed),
+                    ctypes.cast(Hs, ctypes.POINTER(ctypes.c_int32)),
+                    ctypes.cast(Ws, ctypes.POINTER(ctypes.c_int32)))
+    st = ServerStats()
+    check("sne_sched_simulate", lib().sne_sched_simulate(ctypes.byref(cfg), ctypes.byref(st)))
+    return st.as_dict()
+
+
+def _memcpy_d2d(dst: int, src: int, nbytes: int):
+    """Device-to-device copy of nbytes on the current stream (plumbing)."""
+    s = torch.cuda.current_stream()
+    hip = _hip()
+    rc = hip.hipMemcpyAsync(ctypes.c_void_p(dst), ctypes.c_void_p(src), ctypes.c_size_t(nbytes),
+                            3, ctypes.c_void_p(s.cuda_stream))
+    if rc != 0:
+        raise RuntimeError("hipMemcpyAsync failed (%d)" % rc)
+    s.synchronize()
+
+
+_hiplib = None
+
+
+def _hip():
+    global _hiplib
+    if _hiplib is None:
+        _hiplib = ctypes.CDLL("libamdhip64.so")
+        _hiplib.hipMemcpyAsync.restype = ctypes.c_int
+    return _hiplib
 
 
 def _outputs(raw, out_i, normals, mask, want_mask):

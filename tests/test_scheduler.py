@@ -32,3 +32,33 @@ def test_scheduler_cases_sanitized(tmp_path):
     if shutil.which("g++") is None:
         pytest.skip("no g++")
     _build_and_run(tmp_path, ["-fsanitize=address,undefined", "-fno-omit-frame-pointer"])
+
+
+def test_capacity_simulator_20k_fps():
+    """The exported capacity model (host only): 64 streams, 20k frames/s of
+    the serving resolutions against a GPU model; every frame completes, the
+    scheduler batches, latency stays bounded."""
+    import numpy as np
+    from paper_2005_08165_amd import sne
+    shapes = [(240, 320), (480, 640), (720, 1280), (1080, 1920), (2160, 3840)]
+    rng = np.random.default_rng(5001)
+    streams = [shapes[i] for i in rng.integers(0, len(shapes), size=64)]
+    st = sne.simulate(streams, total_rate=20000, duration_s=0.5, gpu_pixels_per_s=4e11,
+                      batch_overhead_s=20e-6, max_inflight=3, budget_bytes=8 << 30)
+    assert st["completed"] == st["submitted"] > 9000
+    assert st["failed"] == 0 and st["rejected_full"] == 0
+    assert st["mean_batch_frames"] > 1.0
+    assert 0 < st["latency_p50"] <= st["latency_p99"] < 5e-3
+    # past capacity the queue grows and the tail latency with it
+    hot = sne.simulate(streams, total_rate=400000, duration_s=0.1, gpu_pixels_per_s=4e11,
+                       batch_overhead_s=20e-6, max_inflight=3, budget_bytes=8 << 30)
+    assert hot["latency_p99"] > 10 * st["latency_p99"]
+
+
+def test_capacity_simulator_budget_admission():
+    """A budget of two 4K outputs: frames wait for memory instead of failing."""
+    from paper_2005_08165_amd import sne
+    st = sne.simulate([(2160, 3840)] * 4, total_rate=2000, duration_s=0.2, gpu_pixels_per_s=4e11,
+                      budget_bytes=2 * 2160 * 3840 * 7 + 4096, max_inflight=3)
+    assert st["completed"] == st["submitted"] > 300
+    assert st["mean_batch_frames"] <= 2.0
