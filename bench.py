@@ -110,6 +110,71 @@ def copy_calibration(torch, nbytes=1 << 30, reps=10):
             "us_per_copy": round(ev / reps * 1e6, 1)}
 
 
+def uneven_batch(torch, S, sne, agg, n_frames=1024, reps=5):
+    """One persistent launch over n_frames frames of sizes drawn uniformly
+    from {240x320, 480x640, 720x1280, 1080x1920}: uint16 millimetre depth in,
+    FP16 normals + mask out (9 B/px), FD gradients, autotuned tile shape."""
+    shapes = S.uneven_sizes(n_frames, seed=3999)
+    uniq = sorted(set(shapes))
+    ctx = sne.Context(0)
+    cams = {sh: S.camera_for(*sh) for sh in uniq}
+    ctx.set_intrinsics_table([cams[sh].as_tuple() for sh in uniq])
+    kidx = {sh: i for i, sh in enumerate(uniq)}
+    # 16 distinct scenes per size, reused across the batch (inputs stay resident)
+    pool = {sh: [S.make_u16(4000 + 97 * j + i, cams[sh], device="cuda").raw for j in range(16)]
+            for i, sh in enumerate(uniq)}
+    frames = [pool[sh][k % 16] for k, sh in enumerate(shapes)]
+    nrm = [torch.empty((3,) + sh, dtype=torch.float16, device="cuda") for sh in shapes]
+    msk = [torch.empty(sh, dtype=torch.uint8, device="cuda") for sh in shapes]
+    ctx.autotune(1080, 1920, 64, "depth_u16", "fd", agg, "f16")
+    ki = [kidx[sh] for sh in shapes]
+    wall, ev = time_launches(torch, lambda i: ctx.estimate_batched(
+        frames, ki, "depth_u16", "fd", agg, "f16", normals=nrm, masks=msk), 1, reps)
+    px = sum(h * w for h, w in shapes)
+    return {"frames": n_frames, "mpix": round(px / 1e6, 1), "agg": agg,
+            "ms_per_launch": round(ev / reps * 1e3, 3),
+            "mpix_per_s": round(px * reps / ev / 1e6, 1),
+            "frames_per_s": round(n_frames * reps / ev, 1),
+            "achieved_GBs": round(px * 9 * reps / ev / 1e9, 1),
+            "frac_of_peak": round(px * 9 * reps / ev / 1e9 / PEAK_HBM_GBS, 4),
+            "note": "wall includes the host descriptor staging of each call"}
+
+
+def serving(torch, S, sne, rates=(20000, 60000, 120000), duration=2.0):
+    """64 sensor streams (resolution per stream drawn with seed 5001 from
+    {240x320 .. 2160x3840}), Poisson arrivals (seed 5000), uint16 depth in a
+    device-resident ring of 2 frames per stream, per-stream intrinsics on the
+    device, FP16 normals, FD-mean; continuous batching with hipGraph replay."""
+    import numpy as np
+    shapes_all = [(240, 320), (480, 640), (720, 1280), (1080, 1920), (2160, 3840)]
+    rng = np.random.default_rng(5001)
+    shapes = [shapes_all[i] for i in rng.integers(0, len(shapes_all), size=64)]
+    cams = [S.camera_for(*sh) for sh in shapes]
+    ctx = sne.Context(0)
+    ctx.set_intrinsics_table([c.as_tuple() for c in cams])
+    rings = [[S.make_u16(5100 + 2 * s + k, cams[s], device="cuda").raw for k in range(2)]
+             for s in range(64)]
+    torch.cuda.synchronize()
+    srv = sne.Server(ctx, "depth_u16", "fd", "mean", "f16", max_inflight=3,
+                     max_batch_frames=256, hbm_budget_bytes=16 << 30, use_graphs=True)
+    out = {"streams": 64, "mean_mpix_per_frame": round(np.mean([h * w for h, w in shapes]) / 1e6, 3),
+           "runs": []}
+    for lam in rates:
+        log("serving at %d frames/s" % lam)
+        st = srv.run_open_loop(rings, total_rate=lam, duration_s=duration, seed=5000,
+                               n_producers=8)
+        out["runs"].append({"offered_fps": lam, "completed": st["completed"],
+                            "p50_ms": round(st["latency_p50"] * 1e3, 3),
+                            "p99_ms": round(st["latency_p99"] * 1e3, 3),
+                            "p999_ms": round(st["latency_p999"] * 1e3, 3),
+                            "mpix_per_s": round(st["mpix_per_s"], 1),
+                            "frames_per_s": round(st["frames_per_s"], 1),
+                            "mean_batch_frames": round(st["mean_batch_frames"], 2),
+                            "hbm_GBs_algorithmic": round(st["mpix_per_s"] * 9 / 1e3, 1)})
+    srv.close()
+    return out
+
+
 def cpu_baseline(host_batch, K, grad, agg, budget_s=20.0):
     """The FP64 oracle, as it stands, on the host's cores over a bounded
     sample of the same workload."""
@@ -145,6 +210,10 @@ def main():
     ap.add_argument("--agg", default="median")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tile", default="", help="force cols_per_lane,rows (skips autotuning)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -171,6 +240,13 @@ def main():
     torch.cuda.synchronize()
 
     ctx = sne.Context(0)
+    tile = None
+    if args.tile:
+        tile = tuple(int(x) for x in args.tile.split(","))
+        ctx.set_tile(*tile)
+    elif not args.no_autotune:
+        log("autotuning the tile shape")
+        tile = ctx.autotune(H, W, B, "depth_f32", args.grad, args.agg, "f32")
 
     def step(i):
         raw, nrm, msk = bufs[i % NBUF]
@@ -184,7 +260,6 @@ def main():
     bytes_per_launch = px * (4 + 12 + 1)
     achieved = bytes_per_launch / (ev / args.steps) / 1e9
     workload = "batch64_480x640_f32depth_%s_%s" % (args.grad, args.agg)
-    tile = ctx.get_tile(H, W, "depth_f32", args.grad, args.agg, "f32")
     res = {
         "metric": "normals Mpix/s (batched, 480x640)",
         "value": round(value, 1),
@@ -201,7 +276,8 @@ def main():
         "config": {"workload": workload, "frames": B, "H": H, "W": W, "input": "f32 depth",
                    "grad": args.grad, "agg": args.agg, "out": "f32 normals + u8 mask",
                    "noise": "0.5% multiplicative Gaussian", "holes": 0.03,
-                   "rotated_buffers": NBUF},
+                   "rotated_buffers": NBUF,
+                   "tile": None if tile is None else {"cols_per_lane": tile[0], "rows": tile[1]}},
         "frames_per_s": round(B * args.steps / wall, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
@@ -215,6 +291,13 @@ def main():
         log("plain single-frame launches")
         res["plain_single_frame"] = [plain_single_frame(torch, S, sne, args.grad, args.agg),
                                      plain_single_frame(torch, S, sne, "fd", "mean")]
+    if not args.no_uneven:
+        log("uneven persistent batch")
+        res["uneven_batch"] = [uneven_batch(torch, S, sne, "mean"),
+                               uneven_batch(torch, S, sne, "median")]
+    if not args.no_serving:
+        log("serving loop")
+        res["serving"] = serving(torch, S, sne)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         host = bufs[0][0].cpu().numpy()

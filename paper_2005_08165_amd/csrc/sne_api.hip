@@ -33,14 +33,17 @@ bool valid_K(const sne_intrinsics *K, int kind) {
 size_t in_elem(int kind) { return kind == SNE_DEPTH_F32 || kind == SNE_DISPARITY_F32 ? 4 : 2; }
 size_t out_elem(int out) { return out == SNE_OUT_F32 ? 4 : 2; }
 
-// 3-row kernels as weights (side, centre) of the central differences.
+// 3-row kernels as the ratio side / centre of their central-difference
+// weights (the kernels' scale cancels from the normal): Sobel 1:2, Scharr
+// 3:10, Prewitt 1:1.  FD uses the centre row only.
 void grad_weights(int grad, float &wa, float &wb) {
     switch (grad) {
-    case SNE_GRAD_SOBEL: wa = 1.f; wb = 2.f; break;
-    case SNE_GRAD_SCHARR: wa = 3.f; wb = 10.f; break;
-    case SNE_GRAD_PREWITT: wa = 1.f; wb = 1.f; break;
-    default: wa = 0.f; wb = 1.f; break;
+    case SNE_GRAD_SOBEL: wa = 0.5f; break;
+    case SNE_GRAD_SCHARR: wa = 0.3f; break;
+    case SNE_GRAD_PREWITT: wa = 1.f; break;
+    default: wa = 0.f; break;
     }
+    wb = 1.f;
 }
 
 bool aligned(const void *p, size_t bytes) { return ((uintptr_t)p % bytes) == 0; }

@@ -32,7 +32,7 @@ struct UniformArgs {
     int32_t nstrips, nbands, rows;  // tile grid of one frame
     int32_t ntiles;                 // B * nbands * nstrips
     int32_t xcd_remap;              // 1: give each XCD a contiguous tile range
-    float wa, wb;                   // 3-row gradient weights (side, centre)
+    float wa, wb;                   // 3-row filters: wa = side / centre weight; wb unused (1)
 };
 
 // Uneven batch, persistent grid pulling tiles from a device counter.

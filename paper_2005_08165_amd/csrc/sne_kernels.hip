@@ -62,6 +62,39 @@ __device__ __forceinline__ float from_right(float old, float src) {
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Min/max of values the compiler cannot prove canonical (they come from
+// other basic blocks or earlier loop iterations) would each be preceded by a
+// quieting v_max x, x, x in IEEE mode.  Every operand below is a finite
+// product or reciprocal or an infinity, never a NaN, so the instructions are
+// issued directly.
+__device__ __forceinline__ float vmin(float a, float b) {
+    float r;
+    asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ float vmax(float a, float b) {
+    float r;
+    asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ float vmin3(float a, float b, float c) {
+    float r;
+    asm("v_min3_f32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+// max(|a|, |b|, |c|)
+__device__ __forceinline__ float vmax3abs(float a, float b, float c) {
+    float r;
+    asm("v_max3_f32 %0, |%1|, |%2|, |%3|" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+__device__ __forceinline__ float vmax3(float a, float b, float c) {
+    float r;
+    asm("v_max3_f32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+
 // ---------------------------------------------------------------- raw input
 template <int KIND> struct Raw;
 template <> struct Raw<KIND_F32> {
@@ -167,7 +200,7 @@ __device__ __forceinline__ void finish_row(const RawRow<KIND, PX> &raw, Row<PX> 
     }
 #pragma unroll
     for (int k = 0; k < PX; ++k) {
-        o.hmin[k] = fminf(fminf(o.z[k], o.z[k + 1]), o.z[k + 2]);
+        o.hmin[k] = vmin3(o.z[k], o.z[k + 1], o.z[k + 2]);
         if constexpr (KIND == KIND_DISP)
             o.D[k] = o.z[k + 2] - o.z[k];
         else
@@ -196,14 +229,49 @@ __device__ __forceinline__ void make_pairs(const Row<PX> &up, const Row<PX> &lo,
     }
 }
 
+// Sorting network of 4 (5 compare-exchanges) as one instruction block.
 __device__ __forceinline__ void sort4(float &a, float &b, float &c, float &d) {
-    const float lo1 = fminf(a, b), hi1 = fmaxf(a, b);
-    const float lo2 = fminf(c, d), hi2 = fmaxf(c, d);
-    const float m1 = fmaxf(lo1, lo2), m2 = fminf(hi1, hi2);
-    a = fminf(lo1, lo2);
-    d = fmaxf(hi1, hi2);
-    b = fminf(m1, m2);
-    c = fmaxf(m1, m2);
+    float oa, ob, oc, od, l1, h1, l2, h2, m1, m2;
+    asm("v_min_f32 %[l1], %[a], %[b]\n\t"
+        "v_max_f32 %[h1], %[a], %[b]\n\t"
+        "v_min_f32 %[l2], %[c], %[d]\n\t"
+        "v_max_f32 %[h2], %[c], %[d]\n\t"
+        "v_max_f32 %[m1], %[l1], %[l2]\n\t"
+        "v_min_f32 %[m2], %[h1], %[h2]\n\t"
+        "v_min_f32 %[oa], %[l1], %[l2]\n\t"
+        "v_max_f32 %[od], %[h1], %[h2]\n\t"
+        "v_min_f32 %[ob], %[m1], %[m2]\n\t"
+        "v_max_f32 %[oc], %[m1], %[m2]"
+        : [oa] "=&v"(oa), [ob] "=&v"(ob), [oc] "=&v"(oc), [od] "=&v"(od), [l1] "=&v"(l1),
+          [h1] "=&v"(h1), [l2] "=&v"(l2), [h2] "=&v"(h2), [m1] "=&v"(m1), [m2] "=&v"(m2)
+        : [a] "v"(a), [b] "v"(b), [c] "v"(c), [d] "v"(d));
+    a = oa;
+    b = ob;
+    c = oc;
+    d = od;
+}
+
+// Order statistics 3 and 4 (0-based) of the union of two sorted quads
+// a0 <= .. <= a3 and b0 <= .. <= b3: the k-th smallest of the union is the
+// minimum over i + j = k + 1 of max(a_i, b_j) (1-based, a_0 = b_0 = -inf,
+// a_5 = b_5 = +inf).
+__device__ __forceinline__ void middle_pair(const float (&t)[8], float &x3, float &x4) {
+    float p, q, r, u, v, w, y, z;
+    asm("v_max_f32 %[p], %[a0], %[b2]\n\t"
+        "v_max_f32 %[q], %[a1], %[b1]\n\t"
+        "v_max_f32 %[r], %[a2], %[b0]\n\t"
+        "v_min3_f32 %[p], %[b3], %[p], %[q]\n\t"
+        "v_min3_f32 %[x3], %[p], %[r], %[a3]\n\t"
+        "v_max_f32 %[u], %[a0], %[b3]\n\t"
+        "v_max_f32 %[v], %[a1], %[b2]\n\t"
+        "v_max_f32 %[w], %[a2], %[b1]\n\t"
+        "v_max_f32 %[y], %[a3], %[b0]\n\t"
+        "v_min_f32 %[z], %[w], %[y]\n\t"
+        "v_min3_f32 %[x4], %[u], %[v], %[z]"
+        : [x3] "=&v"(x3), [x4] "=&v"(x4), [p] "=&v"(p), [q] "=&v"(q), [r] "=&v"(r),
+          [u] "=&v"(u), [v] "=&v"(v), [w] "=&v"(w), [y] "=&v"(y), [z] "=&v"(z)
+        : [a0] "v"(t[0]), [a1] "v"(t[1]), [a2] "v"(t[2]), [a3] "v"(t[3]), [b0] "v"(t[4]),
+          [b1] "v"(t[5]), [b2] "v"(t[6]), [b3] "v"(t[7]));
 }
 
 // Output element stores.
@@ -232,26 +300,41 @@ template <int PX> struct RowState {
 __device__ __forceinline__ float median_pair(float (&t)[8], bool odd) {
     sort4(t[0], t[1], t[2], t[3]);
     sort4(t[4], t[5], t[6], t[7]);
-    // merged order statistics 3 and 4 (0-based) of two sorted quads
-    const float x3 = fminf(fminf(fminf(t[7], fmaxf(t[0], t[6])),
-                                 fminf(fmaxf(t[1], t[5]), fmaxf(t[2], t[4]))),
-                           t[3]);
-    const float x4 = fminf(fminf(fmaxf(t[0], t[7]), fmaxf(t[1], t[6])),
-                           fminf(fmaxf(t[2], t[5]), fmaxf(t[3], t[4])));
+    float x3, x4;
+    middle_pair(t, x3, x4);
     return odd ? x3 : 0.5f * (x3 + x4);
 }
 
-// Median of the kept candidates.  t: 8 candidates in slot order; zj/zc: raw
-// values deciding which slots are left out.  `general` pads left-out slots
-// alternately +inf / -inf; otherwise all 8 are kept.  *none: nothing kept.
-// The network is spelled out in each branch so that the fast path sorts
-// values the compiler knows to be canonical.
-__device__ __forceinline__ float median8(float (&t)[8], const float (&zj)[8], float zc,
-                                         bool general, bool &none) {
+// Candidates t_j = N_j w_j of the 8 slots (see the file header).  Called
+// inside each branch of the aggregation so that the min/max network sees
+// values produced in its own basic block (the compiler then knows they are
+// canonical and inserts no quieting instructions).
+template <int KIND>
+__device__ __forceinline__ void candidates(const float (&Nj)[8], const float (&rj)[8], float zc,
+                                           float (&t)[8]) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        if constexpr (KIND == KIND_DISP)
+            t[j] = -(Nj[j] * zc) * rj[j];
+        else
+            t[j] = fmaf(Nj[j] * zc, rj[j], Nj[j]);
+    }
+}
+
+// Median of the kept candidates; zj/zc decide which slots are left out.
+// `general` pads left-out slots alternately +inf / -inf; otherwise all 8
+// are kept.  *none: nothing kept.
+template <int KIND>
+__device__ __forceinline__ float median8(const float (&Nj)[8], const float (&rj)[8],
+                                         const float (&zj)[8], float zc, bool general,
+                                         bool &none) {
+    float t[8];
     if (!general) {
         none = false;
+        candidates<KIND>(Nj, rj, zc, t);
         return median_pair(t, false);
     }
+    candidates<KIND>(Nj, rj, zc, t);
     float pad = kInf;
     bool all = true;
 #pragma unroll
@@ -265,8 +348,11 @@ __device__ __forceinline__ float median8(float (&t)[8], const float (&zj)[8], fl
     return median_pair(t, pad < 0.f);  // odd number left out -> position 3
 }
 
-__device__ __forceinline__ float mean8(const float (&t)[8], const float (&zj)[8], float zc,
-                                       bool general, bool &none) {
+template <int KIND>
+__device__ __forceinline__ float mean8(const float (&Nj)[8], const float (&rj)[8],
+                                       const float (&zj)[8], float zc, bool general, bool &none) {
+    float t[8];
+    candidates<KIND>(Nj, rj, zc, t);
     if (!general) {
         none = false;
         const float s = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
@@ -318,14 +404,16 @@ __device__ __forceinline__ void tile_row(const FrameDesc &f, const InBuf &ib, in
     for (int k = 0; k < PX; ++k) {
         const int c = k + 1;
         const float zc = rc.z[c];
-        const bool valid = fminf(fminf(rp.hmin[k], rc.hmin[k]), rn.hmin[k]) > 0.f;
+        const bool valid = vmin3(rp.hmin[k], rc.hmin[k], rn.hmin[k]) > 0.f;
         float Gu, Gv;
         if constexpr (FD) {
             Gu = rc.D[k];
             Gv = V[c];
         } else {
-            Gu = fmaf(wa, rp.D[k] + rn.D[k], wb * rc.D[k]);
-            Gv = fmaf(wa, V[c - 1] + V[c + 1], wb * V[c]);
+            // the 3-row filter divided by its centre weight (wa = side /
+            // centre): n' scales as a whole, the normal does not change
+            Gu = fmaf(wa, rp.D[k] + rn.D[k], rc.D[k]);
+            Gv = fmaf(wa, V[c - 1] + V[c + 1], V[c]);
         }
         const float fu = (float)(col + k) - f.u0;
         const float B = fmaf(fu, Gu, fv * Gv);
@@ -336,26 +424,19 @@ __device__ __forceinline__ void tile_row(const FrameDesc &f, const InBuf &ib, in
         const float Nj[8] = {Gu, -Gu, Gv, -Gv, Spp, -Spp, -Spm, Spm};
         const float rj[8] = {rc.rE[c], -rc.rE[c - 1], pd.rS[k], -pu.rS[k],
                              pd.rSE[c], -pu.rSE[k], pd.rSW[k], -pu.rSW[c]};
-        float t[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            if constexpr (KIND == KIND_DISP)
-                t[j] = -(Nj[j] * zc) * rj[j];
-            else
-                t[j] = fmaf(Nj[j] * zc, rj[j], Nj[j]);
-        }
         // A slot is left out iff raw_j == raw, i.e. its pair reciprocal is
         // +-inf.  That is rare in float data: pad only when a valid pixel of
         // this wavefront needs it (the choice is wave-uniform, and both paths
         // give the same result when nothing is left out).
-        const float rmax = fmaxf(fmaxf(fmaxf(fabsf(rj[0]), fabsf(rj[1])), fabsf(rj[2])),
-                                 fmaxf(fmaxf(fmaxf(fabsf(rj[3]), fabsf(rj[4])), fabsf(rj[5])),
-                                       fmaxf(fabsf(rj[6]), fabsf(rj[7]))));
+        // (signs do not matter here: the raw pair values are used)
+        const float rmax = vmax(vmax3abs(rc.rE[c], rc.rE[c - 1], pd.rS[k]),
+                                vmax3abs(pu.rS[k], pd.rSE[c],
+                                         vmax3abs(pu.rSE[k], pd.rSW[k], pu.rSW[c])));
         const bool any_drop = !(rmax < kInf);
         const bool general = __builtin_amdgcn_ballot_w64(valid && any_drop) != 0;
         bool none;
-        const float phi = (AGG == AGG_MEAN) ? mean8(t, zj, zc, general, none)
-                                            : median8(t, zj, zc, general, none);
+        const float phi = (AGG == AGG_MEAN) ? mean8<KIND>(Nj, rj, zj, zc, general, none)
+                                            : median8<KIND>(Nj, rj, zj, zc, general, none);
         const float nx = f.fx * Gu, ny = f.fy * Gv, nz = B + phi;
         const float n2 = fmaf(nx, nx, fmaf(ny, ny, nz * nz));
         const bool deg = none || !(n2 > 0.f);
