@@ -392,7 +392,10 @@ def make_u16(seed: int, cam: Camera, device="cpu", noise: float = 0.005,
     if holes > 0:
         mm = torch.where(torch.rand(z.shape, generator=g, dtype=torch.float64, device=z.device) < holes,
                          torch.zeros_like(mm), mm)
-    return Frame(mm.to(torch.int32).to(torch.uint16), cam, "depth", fr.gt, fr.region, fr.depth64)
+    # int32 -> int16 keeps the low 16 bits; viewing them as uint16 is the
+    # value (a path every torch device supports)
+    u16 = mm.to(torch.int32).to(torch.int16).view(torch.uint16)
+    return Frame(u16, cam, "depth", fr.gt, fr.region, fr.depth64)
 
 
 UNEVEN_SHAPES = ((240, 320), (480, 640), (720, 1280), (1080, 1920))

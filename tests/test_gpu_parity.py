@@ -313,7 +313,10 @@ def _sampled_parity(raw_dev, normals, mask, K, kind, grad, agg, out, n_frames_ch
     raw image, masked pixels are +0, unmasked normals are unit vectors facing
     the camera's side of the surface (z < 0 or tangent)."""
     B, H, W = raw_dev.shape
-    rf = raw_dev.float()
+    if raw_dev.dtype == torch.uint16:   # widen through int16 bits (no uint16 arithmetic)
+        rf = (raw_dev.view(torch.int16).to(torch.int32) & 0xFFFF).float()
+    else:
+        rf = raw_dev.float()
     good = (rf > 0) & torch.isfinite(rf)
     er = -torch.nn.functional.max_pool2d(-good.float().unsqueeze(1), 3, 1, 1).squeeze(1)
     er[:, 0, :] = 0
@@ -364,3 +367,42 @@ def test_full_size_disparity_batch128():
     torch.cuda.synchronize()
     _sampled_parity(raw, n, m, cam.as_tuple(), "disparity_f32", "scharr", "median", "f32", 6,
                     20000, 2, tc=S.ROAD_BASELINE)
+
+
+def test_full_size_uneven_1024_persistent():
+    """1024 frames of sizes drawn from {240x320 .. 1080x1920}, uint16 mm depth,
+    FD-median, FP16 out, one persistent launch with the autotuned tile (the
+    configuration the benchmark times).  Sampled pixels of several frames of
+    every size against the oracle, plus the per-pixel properties."""
+    shapes = S.uneven_sizes(1024, seed=3999)
+    uniq = sorted(set(shapes))
+    cams = {sh: S.camera_for(*sh) for sh in uniq}
+    ctx = sne.Context(0)
+    ctx.set_intrinsics_table([cams[sh].as_tuple() for sh in uniq])
+    kidx = {sh: i for i, sh in enumerate(uniq)}
+    say("generating the uneven pool")
+    pool = {sh: [S.make_u16(4000 + 97 * j + i, cams[sh], device="cuda").raw for j in range(4)]
+            for i, sh in enumerate(uniq)}
+    frames = [pool[sh][k % 4] for k, sh in enumerate(shapes)]
+    ctx.autotune(1080, 1920, 64, "depth_u16", "fd", "median", "f16")
+    normals, masks = ctx.estimate_batched(frames, [kidx[sh] for sh in shapes], "depth_u16", "fd",
+                                          "median", "f16")
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(3)
+    checked = 0
+    for sh in uniq:
+        idx = [k for k, s_ in enumerate(shapes) if s_ == sh][:2]
+        for k in idx:
+            raw = frames[k].unsqueeze(0)
+            _sampled_parity(raw, normals[k].unsqueeze(0), masks[k].unsqueeze(0),
+                            cams[sh].as_tuple(), "depth_u16", "fd", "median", "f16", 1, 20000,
+                            int(rng.integers(1 << 30)))
+            checked += 1
+    assert checked == 2 * len(uniq)
+    # every frame equals its single-frame launch at the same tile shape
+    for k in [0, 511, 1023]:
+        sh = shapes[k]
+        n1, m1 = sne.estimate(frames[k], cams[sh].as_tuple(), "depth_u16", "fd", "median", "f16",
+                              ctx=ctx)
+        torch.cuda.synchronize()
+        assert torch.equal(n1, normals[k]) and torch.equal(m1, masks[k])

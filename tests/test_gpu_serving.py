@@ -116,3 +116,26 @@ def test_open_loop_small():
     assert st["failed"] == 0
     assert 0 < st["latency_p50"] <= st["latency_p99"] < 0.05
     srv.close()
+
+
+def test_served_4k_frames_equal_single_frame():
+    """The largest serving resolution (2160x3840) batched with small frames."""
+    shapes = [(2160, 3840), (240, 320), (1080, 1920)]
+    cams = [S.camera_for(h, w) for h, w in shapes]
+    frames = [S.make_u16(6100 + i, c, device="cuda").raw for i, c in enumerate(cams)]
+    ctx = sne.Context(0)
+    ctx.set_intrinsics_table([c.as_tuple() for c in cams])
+    srv = sne.Server(ctx, "depth_u16", "fd", "median", "f16", max_inflight=2,
+                     hbm_budget_bytes=1 << 30)
+    tickets = {srv.submit(f, s_): s_ for s_, f in enumerate(frames)}
+    srv.drain()
+    done = srv.poll(16)
+    assert len(done) == 3
+    for c in done:
+        s_ = tickets[c.ticket]
+        n, m = srv.result(c)
+        n1, m1 = sne.estimate(frames[s_], cams[s_].as_tuple(), "depth_u16", "fd", "median", "f16")
+        torch.cuda.synchronize()
+        assert torch.equal(n, n1) and torch.equal(m, m1)
+        srv.release(c.ticket)
+    srv.close()
