@@ -82,11 +82,22 @@ __device__ __forceinline__ float vmin3(float a, float b, float c) {
     asm("v_min3_f32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
     return r;
 }
-// max(|a|, |b|, |c|)
-__device__ __forceinline__ float vmax3abs(float a, float b, float c) {
-    float r;
-    asm("v_max3_f32 %0, |%1|, |%2|, |%3|" : "=v"(r) : "v"(a), "v"(b), "v"(c));
-    return r;
+// max over |r_0| .. |r_7|.  The operands are reciprocals straight from
+// v_rcp: a transcendental result needs one wait state before a VALU reads it,
+// which the compiler inserts for its own instructions but not for inline asm,
+// hence the leading s_nop.
+__device__ __forceinline__ float vmax8abs(float r0, float r1, float r2, float r3, float r4,
+                                          float r5, float r6, float r7) {
+    float out, m1, m2, m3;
+    asm("s_nop 0\n\t"
+        "v_max3_f32 %[m1], |%[r0]|, |%[r1]|, |%[r2]|\n\t"
+        "v_max3_f32 %[m2], |%[r3]|, |%[r4]|, |%[r5]|\n\t"
+        "v_max3_f32 %[m3], |%[r6]|, |%[r7]|, %[m1]\n\t"
+        "v_max_f32 %[out], %[m2], %[m3]"
+        : [out] "=&v"(out), [m1] "=&v"(m1), [m2] "=&v"(m2), [m3] "=&v"(m3)
+        : [r0] "v"(r0), [r1] "v"(r1), [r2] "v"(r2), [r3] "v"(r3), [r4] "v"(r4), [r5] "v"(r5),
+          [r6] "v"(r6), [r7] "v"(r7));
+    return out;
 }
 __device__ __forceinline__ float vmax3(float a, float b, float c) {
     float r;
@@ -429,9 +440,8 @@ __device__ __forceinline__ void tile_row(const FrameDesc &f, const InBuf &ib, in
         // this wavefront needs it (the choice is wave-uniform, and both paths
         // give the same result when nothing is left out).
         // (signs do not matter here: the raw pair values are used)
-        const float rmax = vmax(vmax3abs(rc.rE[c], rc.rE[c - 1], pd.rS[k]),
-                                vmax3abs(pu.rS[k], pd.rSE[c],
-                                         vmax3abs(pu.rSE[k], pd.rSW[k], pu.rSW[c])));
+        const float rmax = vmax8abs(rc.rE[c], rc.rE[c - 1], pd.rS[k], pu.rS[k], pd.rSE[c],
+                                    pu.rSE[k], pd.rSW[k], pu.rSW[c]);
         const bool any_drop = !(rmax < kInf);
         const bool general = __builtin_amdgcn_ballot_w64(valid && any_drop) != 0;
         bool none;
