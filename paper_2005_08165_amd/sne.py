@@ -268,12 +268,12 @@ class Context:
         return estimate_uniform(raw, K, kind, grad, agg, out, normals, mask, want_mask, stream,
                                 ctx=self)
 
-    def estimate_batched(self, frames: Sequence[torch.Tensor], k_index: Sequence[int],
-                         kind="depth_u16", grad="fd", agg="mean", out="f16",
-                         normals: Optional[Sequence[torch.Tensor]] = None,
-                         masks: Optional[Sequence[Optional[torch.Tensor]]] = None, stream=None):
-        """One persistent launch over frames of any sizes.  Returns the lists
-        (normals, masks); outputs are allocated unless given."""
+    def prepare_batched(self, frames: Sequence[torch.Tensor], k_index: Sequence[int],
+                        kind="depth_u16", out="f16",
+                        normals: Optional[Sequence[torch.Tensor]] = None,
+                        masks: Optional[Sequence[Optional[torch.Tensor]]] = None):
+        """Descriptor array (host, ctypes) of an uneven batch, reusable across
+        launches, with the outputs it points to."""
         kind_i = _enum(KIND, kind, "kind")
         out_i = _enum(OUT, out, "out")
         n = len(frames)
@@ -293,9 +293,24 @@ class Context:
                                  None if m is None else m.data_ptr(), H, W, _row_pitch(f),
                                  _row_pitch(normals[i]), 0 if m is None else _row_pitch(m),
                                  int(k_index[i]), 0)
+        return descs, normals, masks
+
+    def run_batched(self, descs, kind="depth_u16", grad="fd", agg="mean", out="f16",
+                    stream=None):
+        """sne_estimate_batched on a prepared descriptor array."""
         check("sne_estimate_batched",
-              lib().sne_estimate_batched(self._h, descs, n, kind_i, _enum(GRAD, grad, "grad"),
-                                         _enum(AGG, agg, "agg"), out_i, _stream(stream)))
+              lib().sne_estimate_batched(self._h, descs, len(descs), _enum(KIND, kind, "kind"),
+                                         _enum(GRAD, grad, "grad"), _enum(AGG, agg, "agg"),
+                                         _enum(OUT, out, "out"), _stream(stream)))
+
+    def estimate_batched(self, frames: Sequence[torch.Tensor], k_index: Sequence[int],
+                         kind="depth_u16", grad="fd", agg="mean", out="f16",
+                         normals: Optional[Sequence[torch.Tensor]] = None,
+                         masks: Optional[Sequence[Optional[torch.Tensor]]] = None, stream=None):
+        """One persistent launch over frames of any sizes.  Returns the lists
+        (normals, masks); outputs are allocated unless given."""
+        descs, normals, masks = self.prepare_batched(frames, k_index, kind, out, normals, masks)
+        self.run_batched(descs, kind, grad, agg, out, stream)
         return normals, masks
 
 
