@@ -214,7 +214,8 @@ def main():
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--tile", default="", help="force cols_per_lane,rows (skips autotuning)")
+    ap.add_argument("--tile", default="",
+                    help="force cols_per_lane,rows[,lanes] (skips autotuning)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -245,6 +246,7 @@ def main():
     if args.tile:
         tile = tuple(int(x) for x in args.tile.split(","))
         ctx.set_tile(*tile)
+        tile = ctx.get_tile(H, W, "depth_f32", args.grad, args.agg, "f32")
     elif not args.no_autotune:
         log("autotuning the tile shape")
         tile = ctx.autotune(H, W, B, "depth_f32", args.grad, args.agg, "f32")
@@ -278,7 +280,8 @@ def main():
                    "grad": args.grad, "agg": args.agg, "out": "f32 normals + u8 mask",
                    "noise": "0.5% multiplicative Gaussian", "holes": 0.03,
                    "rotated_buffers": NBUF,
-                   "tile": None if tile is None else {"cols_per_lane": tile[0], "rows": tile[1]}},
+                   "tile": None if tile is None else {"cols_per_lane": tile[0], "rows": tile[1],
+                                                      "lanes": tile[2]}},
         "frames_per_s": round(B * args.steps / wall, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),

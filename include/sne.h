@@ -143,12 +143,16 @@ int sne_set_intrinsics_table(sne_ctx *ctx, const sne_intrinsics *K, int32_t n);
 int sne_estimate_batched(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int grad,
                          int agg, int out_type, void *stream);
 
-/* Tile shape: each 64-lane wavefront covers `cols_per_lane * 64` columns by
- * `rows` rows of a frame.  cols_per_lane is 1, 2 or 4 (vector width of the
- * loads and stores); rows is 1..1024. */
+/* Tile shape: each group of `lanes` lanes of a wavefront covers
+ * `cols_per_lane * lanes` columns by `rows` rows of a frame.  cols_per_lane is
+ * 1, 2 or 4 (vector width of the loads and stores); rows is 1..1024; lanes is
+ * 64 (one tile per wavefront) or 32 (half-wave mode: the two halves take
+ * vertically adjacent tiles of the same strip, which leaves no idle lane when
+ * the width is an odd multiple of 32 * cols_per_lane; 0 means 64). */
 typedef struct {
     int32_t cols_per_lane;
     int32_t rows;
+    int32_t lanes;
 } sne_tile;
 
 /* Force a tile shape for every later call on ctx (rows = 0 restores the

@@ -57,9 +57,13 @@ def _compile(unit):
     return "\n".join(noise)
 
 
-def build(jobs: int = 0, verbose: bool = False) -> str:
-    os.makedirs(OBJ, exist_ok=True)
-    units = _units()
+def build(jobs: int = 0, verbose: bool = False, out: str = LIB, defines=()) -> str:
+    """Compile and link; `defines` (e.g. ["SNE_PREFETCH_ROWS=2"]) and `out`
+    produce an alternative build for experiments."""
+    obj_dir = OBJ if out == LIB else os.path.join(PKG, "_build_" + os.path.basename(out))
+    os.makedirs(obj_dir, exist_ok=True)
+    units = [(s, os.path.join(obj_dir, os.path.basename(o)), e + ["-D" + d for d in defines])
+             for s, o, e in _units()]
     jobs = jobs or min(len(units), os.cpu_count() or 4)
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         logs = list(ex.map(_compile, units))
@@ -67,18 +71,20 @@ def build(jobs: int = 0, verbose: bool = False) -> str:
         for l in logs:
             if l:
                 print(l, file=sys.stderr)
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tmp = out + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + [u[1] for u in units]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed: %s\n%s%s" % (" ".join(cmd), r.stdout, r.stderr))
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=0)
     ap.add_argument("-v", "--verbose", action="store_true")
+    ap.add_argument("--out", default=LIB)
+    ap.add_argument("-D", dest="defines", action="append", default=[])
     args = ap.parse_args()
-    print(build(args.jobs, args.verbose))
+    print(build(args.jobs, args.verbose, os.path.abspath(args.out), args.defines))

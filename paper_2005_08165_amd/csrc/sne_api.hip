@@ -65,24 +65,28 @@ int max_px(const void *in, const void *out, const uint8_t *mask, int W, int64_t 
 int batch_class(int64_t B) { return B <= 1 ? 0 : (B <= 8 ? 1 : 2); }
 
 // Heuristic tile shape when nothing is cached: fewest idle lanes in the last
-// strip, then enough wavefronts to cover every CU several times.
+// strip (full or half-wave strips), then enough wavefronts to cover every CU
+// several times.
 TileChoice default_tile(const sne_ctx *ctx, int H, int W, int64_t B, int pxmax) {
-    int best = 1;
+    TileChoice best{1, 2, 1, 0};
     int64_t best_waste = -1;
     for (int px : {4, 2, 1}) {
         if (px > pxmax) continue;
-        const int64_t span = 64 * px;
-        const int64_t waste = ((W + span - 1) / span) * span - W;
-        if (best_waste < 0 || waste < best_waste) {
-            best = px;
-            best_waste = waste;
+        for (int half : {0, 1}) {
+            TileChoice t{px, 2, 1, half};
+            const int64_t span = tile_cols(t);
+            const int64_t waste = ((W + span - 1) / span) * span - W;
+            if (best_waste < 0 || waste < best_waste) {
+                best = t;
+                best_waste = waste;
+            }
         }
     }
-    const int64_t nstrips = (W + 64 * best - 1) / (64 * best);
+    const int64_t nstrips = tile_nstrips(W, best);
     const int64_t target = (int64_t)(ctx ? ctx->num_cu : 256) * 16;  // wavefronts
-    int64_t rows = (B * H * nstrips) / std::max<int64_t>(target, 1);
-    rows = std::min<int64_t>(std::max<int64_t>(rows, 2), 32);
-    return TileChoice{best, (int)rows, 1};
+    int64_t rows = (B * H * nstrips) / std::max<int64_t>(target, 1) / (best.half ? 2 : 1);
+    best.rows = (int)std::min<int64_t>(std::max<int64_t>(rows, 2), 32);
+    return best;
 }
 
 TileChoice pick_tile(const sne_ctx *ctx, int H, int W, int64_t B, const Variant &v, int pxmax) {
@@ -175,15 +179,15 @@ int uniform_impl(sne_ctx *ctx, const void *in, int32_t B, int32_t H, int32_t W, 
                              mask_fs, plane, kind, out_type);
     TileChoice t = force ? *force : pick_tile(ctx, H, W, B, v, pxmax);
     if (t.px > pxmax || t.rows < 1) return SNE_ERR_ARG;
-    v.px = t.px;
+    v.px = kernel_px(t);
     UniformArgs a;
     a.f = make_desc(in, normals, mask, H, W, in_pitch, out_pitch, mask_pitch, *K);
     a.in_fstride = in_fs;
     a.out_fstride = out_fs;
     a.mask_fstride = mask_fs;
     a.B = B;
-    a.nstrips = (W + 64 * t.px - 1) / (64 * t.px);
-    a.nbands = (H + t.rows - 1) / t.rows;
+    a.nstrips = tile_nstrips(W, t);
+    a.nbands = tile_nbands(H, t);
     a.rows = t.rows;
     const int64_t ntiles = (int64_t)B * a.nstrips * a.nbands;
     if (ntiles > INT32_MAX - 4 * kWavesPerBlock) return SNE_ERR_BUDGET;
@@ -261,7 +265,7 @@ int batched_impl(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int
     Variant v{kind, grad, agg, out_type, 1};
     TileChoice t = force ? *force : pick_tile(ctx, maxH, maxW, n, v, pxmax);
     if (t.px > pxmax || t.rows < 1) return SNE_ERR_ARG;
-    v.px = t.px;
+    v.px = kernel_px(t);
     Slot &s = ctx->slots[ctx->next_slot];
     ctx->next_slot = (ctx->next_slot + 1) % kSlots;
     hipSetDevice(ctx->device);
@@ -279,8 +283,8 @@ int batched_impl(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int
         hf[i] = make_desc(f.in, f.normals, f.mask, f.H, f.W, f.in_pitch, f.out_pitch,
                           f.mask_pitch, unused);
         hf[i].k_index = f.k_index;
-        const int ns = (f.W + 64 * t.px - 1) / (64 * t.px);
-        const int nb = (f.H + t.rows - 1) / t.rows;
+        const int ns = tile_nstrips(f.W, t);
+        const int nb = tile_nbands(f.H, t);
         hstart[i] = (int32_t)tiles;
         hns[i] = ns;
         tiles += (int64_t)ns * nb;
@@ -439,13 +443,14 @@ int sne_estimate_batched(sne_ctx *ctx, const sne_frame *frames, int32_t n, int k
 int sne_set_tile(sne_ctx *ctx, const sne_tile *tile) {
     if (!ctx || !tile) return SNE_ERR_ARG;
     if (tile->rows == 0) {
-        ctx->forced = TileChoice{0, 0, 0};
+        ctx->forced = TileChoice{0, 0, 0, 0};
         return SNE_OK;
     }
     if (!(tile->cols_per_lane == 1 || tile->cols_per_lane == 2 || tile->cols_per_lane == 4) ||
-        tile->rows < 1 || tile->rows > 1024)
+        tile->rows < 1 || tile->rows > 1024 ||
+        !(tile->lanes == 0 || tile->lanes == 64 || tile->lanes == 32))
         return SNE_ERR_ARG;
-    ctx->forced = TileChoice{tile->cols_per_lane, tile->rows, 1};
+    ctx->forced = TileChoice{tile->cols_per_lane, tile->rows, 1, tile->lanes == 32 ? 1 : 0};
     return SNE_OK;
 }
 
@@ -456,6 +461,7 @@ int sne_get_tile(sne_ctx *ctx, int32_t H, int32_t W, int kind, int grad, int agg
     TileChoice t = pick_tile(ctx, H, W, 1, v, 4);
     tile->cols_per_lane = t.px;
     tile->rows = t.rows;
+    tile->lanes = t.half ? 32 : 64;
     return SNE_OK;
 }
 
@@ -476,7 +482,7 @@ int sne_autotune(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int gr
         hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         rc = SNE_ERR_HIP;
     }
-    TileChoice best{0, 0, 0};
+    TileChoice best{0, 0, 0, 0};
     if (rc == SNE_OK) {
         const int threads = 256;
         const int blocks = (int)((npx + threads - 1) / threads);
@@ -495,8 +501,9 @@ int sne_autotune(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int gr
             if (px > pxmax) continue;
             for (int rows : rows_set) {
                 if (rows > 2 * H) continue;
-                for (int remap : {0, 1}) {
-                    TileChoice t{px, rows, remap};
+                for (int tk = 0; tk < 4; ++tk) {
+                    const int remap = tk & 1, half = tk >> 1;
+                    TileChoice t{px, rows, remap, half};
                     float samples[5];
                     bool ok = true;
                     for (int it = 0; it < 7 && ok; ++it) {
@@ -535,6 +542,7 @@ int sne_autotune(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int gr
     if (tile) {
         tile->cols_per_lane = best.px;
         tile->rows = best.rows;
+        tile->lanes = best.half ? 32 : 64;
     }
     return SNE_OK;
 }
@@ -547,8 +555,9 @@ int sne_autotune_save(const sne_ctx *ctx, const char *path) {
     for (const auto &kv : ctx->cache) {
         const TileKey &k = kv.first;
         const TileChoice &t = kv.second;
-        std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d %d\n", ctx->arch.c_str(), kVersion, k.H,
-                     k.W, k.bclass, k.kind, k.grad, k.agg, k.out, t.px, t.rows, t.remap);
+        std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d %d %d\n", ctx->arch.c_str(), kVersion,
+                     k.H, k.W, k.bclass, k.kind, k.grad, k.agg, k.out, t.px, t.rows, t.remap,
+                     t.half);
     }
     const bool ok = std::fclose(f) == 0;
     return ok ? SNE_OK : SNE_ERR_IO;
@@ -562,15 +571,17 @@ int sne_autotune_load(sne_ctx *ctx, const char *path) {
     while (std::fgets(line, sizeof line, f)) {
         if (line[0] == '#') continue;
         char arch[128];
-        int ver, H, W, bc, kind, grad, agg, out, px, rows, remap;
-        if (std::sscanf(line, "%127s %d %d %d %d %d %d %d %d %d %d %d", arch, &ver, &H, &W, &bc,
-                        &kind, &grad, &agg, &out, &px, &rows, &remap) != 12)
-            continue;
+        int ver, H, W, bc, kind, grad, agg, out, px, rows, remap, half = 0;
+        const int got = std::sscanf(line, "%127s %d %d %d %d %d %d %d %d %d %d %d %d", arch, &ver,
+                                    &H, &W, &bc, &kind, &grad, &agg, &out, &px, &rows, &remap,
+                                    &half);
+        if (got != 12 && got != 13) continue;
         if (ctx->arch != arch || ver != kVersion) continue;
         if (!valid_enum(kind, grad, agg, out) || !(px == 1 || px == 2 || px == 4) || rows < 1 ||
             rows > 1024)
             continue;
-        ctx->cache[TileKey{H, W, bc, kind, grad, agg, out}] = TileChoice{px, rows, remap ? 1 : 0};
+        ctx->cache[TileKey{H, W, bc, kind, grad, agg, out}] =
+            TileChoice{px, rows, remap ? 1 : 0, half ? 1 : 0};
     }
     std::fclose(f);
     return SNE_OK;

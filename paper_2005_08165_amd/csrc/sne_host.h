@@ -25,7 +25,17 @@ struct TileKey {
 };
 struct TileChoice {
     int px, rows, remap;
+    int half = 0;  // 1: half-wave mode (two 32-lane tiles per wavefront)
 };
+
+// Columns one tile covers, row bands per frame and the kernel selector.
+inline int tile_cols(const TileChoice &t) { return (t.half ? 32 : 64) * t.px; }
+inline int tile_nstrips(int W, const TileChoice &t) { return (W + tile_cols(t) - 1) / tile_cols(t); }
+inline int tile_nbands(int H, const TileChoice &t) {
+    const int nb = (H + t.rows - 1) / t.rows;
+    return t.half ? (nb + 1) / 2 : nb;  // a half-wave tile is a pair of bands
+}
+inline int kernel_px(const TileChoice &t) { return t.px + (t.half ? 100 : 0); }
 
 // Device tables of one in-flight uneven batch.
 struct Slot {

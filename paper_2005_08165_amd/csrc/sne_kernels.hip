@@ -41,6 +41,11 @@
 #error "compile with -DSNE_KIND=<0..3>"
 #endif
 
+// Rows loaded ahead of the row being finished (1 or 2).
+#ifndef SNE_PREFETCH_ROWS
+#define SNE_PREFETCH_ROWS 1
+#endif
+
 namespace sne {
 namespace {
 
@@ -192,13 +197,34 @@ template <int PX> struct Row {
     float rE[PX + 1];  // rE[i] = 1 / (z[i+1] - z[i])
 };
 
-template <int KIND, int PX>
-__device__ __forceinline__ void finish_row(const RawRow<KIND, PX> &raw, Row<PX> &o) {
+// Lanes at the inner edges of two half-wave tiles (31 and 32) take their
+// halo sample instead of the neighbour across the boundary.
+struct Edges {
+    bool left;   // lane 32 in half-wave mode
+    bool right;  // lane 31 in half-wave mode
+};
+
+template <bool HALF>
+__device__ __forceinline__ float left_of(float old, float src, const Edges &e) {
+    const float v = from_left(old, src);
+    if constexpr (HALF) return e.left ? old : v;
+    return v;
+}
+template <bool HALF>
+__device__ __forceinline__ float right_of(float old, float src, const Edges &e) {
+    const float v = from_right(old, src);
+    if constexpr (HALF) return e.right ? old : v;
+    return v;
+}
+
+template <int KIND, int PX, bool HALF>
+__device__ __forceinline__ void finish_row(const RawRow<KIND, PX> &raw, Row<PX> &o,
+                                           const Edges &e) {
     const float h = Raw<KIND>::value(raw.h);
 #pragma unroll
     for (int k = 0; k < PX; ++k) o.z[k + 1] = Raw<KIND>::value(raw.x.v[k]);
-    o.z[0] = from_left(h, o.z[PX]);
-    o.z[PX + 1] = from_right(h, o.z[1]);
+    o.z[0] = left_of<HALF>(h, o.z[PX], e);
+    o.z[PX + 1] = right_of<HALF>(h, o.z[1], e);
     if constexpr (KIND == KIND_DISP) {
 #pragma unroll
         for (int i = 0; i < PX + 2; ++i) o.s[i] = o.z[i];
@@ -206,8 +232,8 @@ __device__ __forceinline__ void finish_row(const RawRow<KIND, PX> &raw, Row<PX> 
         const float hs = rcp(h);
 #pragma unroll
         for (int k = 1; k <= PX; ++k) o.s[k] = rcp(o.z[k]);
-        o.s[0] = from_left(hs, o.s[PX]);
-        o.s[PX + 1] = from_right(hs, o.s[1]);
+        o.s[0] = left_of<HALF>(hs, o.s[PX], e);
+        o.s[PX + 1] = right_of<HALF>(hs, o.s[1], e);
     }
 #pragma unroll
     for (int k = 0; k < PX; ++k) {
@@ -382,14 +408,16 @@ __device__ __forceinline__ float mean8(const float (&Nj)[8], const float (&rj)[8
 }
 
 // Output row r of a tile from the window (prev, cur, next); `pend` holds the
-// raw loads of row r + 1 on entry and those of row r + 2 on exit.
-template <int KIND, bool FD, int AGG, int OUT, int PX>
-__device__ __forceinline__ void tile_row(const FrameDesc &f, const InBuf &ib, int r, int col,
-                                         int col_off, int halo_off, float wa, float wb,
-                                         RawRow<KIND, PX> &pend, const RowState<PX> &prev,
-                                         RowState<PX> &cur, RowState<PX> &next) {
-    finish_row<KIND, PX>(pend, next.row);
-    load_raw<KIND, PX>(ib, r + 2, col_off, halo_off, pend);  // prefetch
+// raw loads of row r + 1 on entry and those of row r + 1 + SNE_PREFETCH_ROWS
+// on exit.
+template <int KIND, bool FD, int AGG, int OUT, int PX, bool HALF>
+__device__ __forceinline__ void tile_row(const FrameDesc &f, const InBuf &ib, int r, int rend,
+                                         int col, int col_off, int halo_off, const Edges &e,
+                                         float wa, float wb, RawRow<KIND, PX> &pend,
+                                         const RowState<PX> &prev, RowState<PX> &cur,
+                                         RowState<PX> &next) {
+    finish_row<KIND, PX, HALF>(pend, next.row, e);
+    load_raw<KIND, PX>(ib, r + 1 + SNE_PREFETCH_ROWS, col_off, halo_off, pend);  // prefetch
     make_pairs<PX>(cur.row, next.row, cur.below);
     const Row<PX> &rp = prev.row, &rc = cur.row, &rn = next.row;
     const Pairs<PX> &pu = prev.below, &pd = cur.below;
@@ -457,7 +485,7 @@ __device__ __forceinline__ void tile_row(const FrameDesc &f, const InBuf &ib, in
         oz.v[k] = Out<OUT>::cvt(keep ? nz * inv : (valid ? -1.f : 0.f));
         mk[k] = valid ? 1 : 0;
     }
-    if (col < f.W) {
+    if (col < f.W && r < rend) {
         OT *o = static_cast<OT *>(f.out) + (int64_t)r * f.out_pitch + col;
         *reinterpret_cast<Vec<OT, PX> *>(o) = ox;
         *reinterpret_cast<Vec<OT, PX> *>(o + f.out_plane) = oy;
@@ -472,39 +500,71 @@ __device__ __forceinline__ void tile_row(const FrameDesc &f, const InBuf &ib, in
     }
 }
 
-// One tile: columns [c0, c0 + 64 PX) x rows [r0, r1) of frame f.  The row
-// loop is unrolled three times with the window's roles rotating, so no
-// register state is copied between rows.
-template <int KIND, bool FD, int AGG, int OUT, int PX>
-__device__ __forceinline__ void run_tile(const FrameDesc &f, int c0, int r0, int r1, float wa,
+// One tile: columns [c0, c0 + 64 PX) x rows [r0, r0 + rows) of frame f, or
+// in half-wave mode two tiles of 32 PX columns: lanes 0-31 take rows
+// [r0, r0 + rows), lanes 32-63 rows [r0 + rows, r0 + 2 rows) of the same
+// strip (the frame, hence the buffer resource, stays wave-uniform).  Rows
+// past the frame read as 0 and are not stored.  The row loop is unrolled three
+// times with the window's roles rotating, so no register state is copied.
+template <int KIND, bool FD, int AGG, int OUT, int PX, bool HALF>
+__device__ __forceinline__ void run_tile(const FrameDesc &f, int c0, int r0, int rows, float wa,
                                          float wb) {
     using T = typename Raw<KIND>::T;
+    constexpr int kLanes = HALF ? kWave / 2 : kWave;
     const int lane = threadIdx.x & (kWave - 1);
-    const int col = c0 + lane * PX;
+    const int llane = lane & (kLanes - 1);
+    const int col = c0 + llane * PX;
     const int esz = (int)sizeof(T);
     const InBuf ib = make_inbuf(f.in, f.in_pitch, f.H, esz);
     const int col_off = col < f.W ? col * esz : kOOB;
     int hcol = -1;
-    if (lane == 0) hcol = c0 - 1;
-    if (lane == kWave - 1) hcol = c0 + kWave * PX;
+    if (llane == 0) hcol = c0 - 1;
+    if (llane == kLanes - 1) hcol = c0 + kLanes * PX;
     const int halo_off = (hcol >= 0 && hcol < f.W) ? hcol * esz : kOOB;
+    const Edges e{HALF && lane == kLanes, HALF && lane == kLanes - 1};
+    const int rb = HALF ? r0 + (lane >> 5) * rows : r0;  // first row of this lane's band
+    const int rend = min(rb + rows, f.H);                // rows stored: [rb, rend)
+    const int n = HALF ? rows : rend - rb;               // wave-uniform iterations
 
-    RawRow<KIND, PX> pend;
+    RawRow<KIND, PX> p0;
     RowState<PX> A, B, C;
-    load_raw<KIND, PX>(ib, r0 - 1, col_off, halo_off, pend);
-    finish_row<KIND, PX>(pend, A.row);
-    load_raw<KIND, PX>(ib, r0, col_off, halo_off, pend);
-    finish_row<KIND, PX>(pend, B.row);
+    load_raw<KIND, PX>(ib, rb - 1, col_off, halo_off, p0);
+    finish_row<KIND, PX, HALF>(p0, A.row, e);
+    load_raw<KIND, PX>(ib, rb, col_off, halo_off, p0);
+    finish_row<KIND, PX, HALF>(p0, B.row, e);
     make_pairs<PX>(A.row, B.row, A.below);
-    load_raw<KIND, PX>(ib, r0 + 1, col_off, halo_off, pend);
-
-    for (int r = r0; r < r1; r += 3) {
-        tile_row<KIND, FD, AGG, OUT, PX>(f, ib, r, col, col_off, halo_off, wa, wb, pend, A, B, C);
-        if (r + 1 >= r1) break;
-        tile_row<KIND, FD, AGG, OUT, PX>(f, ib, r + 1, col, col_off, halo_off, wa, wb, pend, B, C, A);
-        if (r + 2 >= r1) break;
-        tile_row<KIND, FD, AGG, OUT, PX>(f, ib, r + 2, col, col_off, halo_off, wa, wb, pend, C, A, B);
+    load_raw<KIND, PX>(ib, rb + 1, col_off, halo_off, p0);
+#define SNE_ROW(I, P, X, Y, Z)                                                                   \
+    tile_row<KIND, FD, AGG, OUT, PX, HALF>(f, ib, rb + (I), rend, col, col_off, halo_off, e, wa, \
+                                           wb, P, X, Y, Z)
+#if SNE_PREFETCH_ROWS == 1
+    for (int i = 0; i < n; i += 3) {
+        SNE_ROW(i, p0, A, B, C);
+        if (i + 1 >= n) break;
+        SNE_ROW(i + 1, p0, B, C, A);
+        if (i + 2 >= n) break;
+        SNE_ROW(i + 2, p0, C, A, B);
     }
+#else
+    // two rows in flight: p0 and p1 alternate, the window roles rotate with
+    // period 3, so the loop is unrolled six times
+    RawRow<KIND, PX> p1;
+    load_raw<KIND, PX>(ib, rb + 2, col_off, halo_off, p1);
+    for (int i = 0; i < n; i += 6) {
+        SNE_ROW(i, p0, A, B, C);
+        if (i + 1 >= n) break;
+        SNE_ROW(i + 1, p1, B, C, A);
+        if (i + 2 >= n) break;
+        SNE_ROW(i + 2, p0, C, A, B);
+        if (i + 3 >= n) break;
+        SNE_ROW(i + 3, p1, A, B, C);
+        if (i + 4 >= n) break;
+        SNE_ROW(i + 4, p0, B, C, A);
+        if (i + 5 >= n) break;
+        SNE_ROW(i + 5, p1, C, A, B);
+    }
+#endif
+#undef SNE_ROW
 }
 
 // Blocks are handed to the 8 XCDs round-robin; renumber them so that XCD x
@@ -516,7 +576,7 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     return x * q + min(x, rem) + i;
 }
 
-template <int KIND, bool FD, int AGG, int OUT, int PX>
+template <int KIND, bool FD, int AGG, int OUT, int PX, bool HALF>
 __global__ __launch_bounds__(kBlock) void sne_uniform_kernel(UniformArgs a) {
     const int b = a.xcd_remap ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     // wave-uniform by construction; readfirstlane lets the compiler keep the
@@ -534,14 +594,15 @@ __global__ __launch_bounds__(kBlock) void sne_uniform_kernel(UniformArgs a) {
     f.in = static_cast<const IT *>(a.f.in) + frame * a.in_fstride;
     f.out = static_cast<OT *>(a.f.out) + frame * a.out_fstride;
     if (f.mask) f.mask = a.f.mask + frame * a.mask_fstride;
-    const int r0 = band * a.rows;
-    const int r1 = min(r0 + a.rows, f.H);
-    run_tile<KIND, FD, AGG, OUT, PX>(f, strip * kWave * PX, r0, r1, a.wa, a.wb);
+    // half-wave mode: a "band" is a pair of bands and a strip is 32 PX wide
+    const int r0 = band * a.rows * (HALF ? 2 : 1);
+    run_tile<KIND, FD, AGG, OUT, PX, HALF>(f, strip * (HALF ? kWave / 2 : kWave) * PX, r0, a.rows,
+                                           a.wa, a.wb);
 }
 
 // Persistent uneven batch: every wavefront pulls `chunk` consecutive tiles at
 // a time from a device counter until the queue is drained.
-template <int KIND, bool FD, int AGG, int OUT, int PX>
+template <int KIND, bool FD, int AGG, int OUT, int PX, bool HALF>
 __global__ __launch_bounds__(kBlock) void sne_batch_kernel(BatchArgs a) {
     const int lane = threadIdx.x & (kWave - 1);
     const int nframes = a.counts ? a.counts[0] : a.nframes;
@@ -570,19 +631,23 @@ __global__ __launch_bounds__(kBlock) void sne_batch_kernel(BatchArgs a) {
             const int ns = a.nstrips[frame];
             const int band = local / ns;
             const int strip = local - band * ns;
-            const int r0 = band * a.rows;
-            const int r1 = min(r0 + a.rows, f.H);
-            run_tile<KIND, FD, AGG, OUT, PX>(f, strip * kWave * PX, r0, r1, a.wa, a.wb);
+            const int r0 = band * a.rows * (HALF ? 2 : 1);
+            run_tile<KIND, FD, AGG, OUT, PX, HALF>(f, strip * (HALF ? kWave / 2 : kWave) * PX, r0,
+                                                   a.rows, a.wa, a.wb);
         }
     }
 }
 
 template <int KIND, bool FD, int AGG, int OUT>
 hipError_t uniform_px(int px, const UniformArgs &a, int grid, hipStream_t s) {
+    // px: columns per lane, + 100 for the half-wave mode
     switch (px) {
-    case 1: hipLaunchKernelGGL((sne_uniform_kernel<KIND, FD, AGG, OUT, 1>), dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((sne_uniform_kernel<KIND, FD, AGG, OUT, 2>), dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((sne_uniform_kernel<KIND, FD, AGG, OUT, 4>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((sne_uniform_kernel<KIND, FD, AGG, OUT, 1, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((sne_uniform_kernel<KIND, FD, AGG, OUT, 2, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((sne_uniform_kernel<KIND, FD, AGG, OUT, 4, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 101: hipLaunchKernelGGL((sne_uniform_kernel<KIND, FD, AGG, OUT, 1, true>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 102: hipLaunchKernelGGL((sne_uniform_kernel<KIND, FD, AGG, OUT, 2, true>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 104: hipLaunchKernelGGL((sne_uniform_kernel<KIND, FD, AGG, OUT, 4, true>), dim3(grid), dim3(kBlock), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -590,10 +655,14 @@ hipError_t uniform_px(int px, const UniformArgs &a, int grid, hipStream_t s) {
 
 template <int KIND, bool FD, int AGG, int OUT>
 hipError_t batch_px(int px, const BatchArgs &a, int grid, hipStream_t s) {
+    // px: columns per lane, + 100 for the half-wave mode
     switch (px) {
-    case 1: hipLaunchKernelGGL((sne_batch_kernel<KIND, FD, AGG, OUT, 1>), dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((sne_batch_kernel<KIND, FD, AGG, OUT, 2>), dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((sne_batch_kernel<KIND, FD, AGG, OUT, 4>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((sne_batch_kernel<KIND, FD, AGG, OUT, 1, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((sne_batch_kernel<KIND, FD, AGG, OUT, 2, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((sne_batch_kernel<KIND, FD, AGG, OUT, 4, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 101: hipLaunchKernelGGL((sne_batch_kernel<KIND, FD, AGG, OUT, 1, true>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 102: hipLaunchKernelGGL((sne_batch_kernel<KIND, FD, AGG, OUT, 2, true>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 104: hipLaunchKernelGGL((sne_batch_kernel<KIND, FD, AGG, OUT, 4, true>), dim3(grid), dim3(kBlock), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

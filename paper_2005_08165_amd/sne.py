@@ -17,7 +17,8 @@ from typing import Iterable, List, Optional, Sequence, Tuple
 import torch
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libsne.so")
+# SNE_LIBRARY selects another build of the same library (e.g. an experiment)
+LIB_PATH = os.environ.get("SNE_LIBRARY", os.path.join(PKG, "libsne.so"))
 HEADER = os.path.join(os.path.dirname(PKG), "include", "sne.h")
 
 SNE_OK = 0
@@ -52,7 +53,8 @@ class FrameDesc(ctypes.Structure):
 
 
 class Tile(ctypes.Structure):
-    _fields_ = [("cols_per_lane", ctypes.c_int32), ("rows", ctypes.c_int32)]
+    _fields_ = [("cols_per_lane", ctypes.c_int32), ("rows", ctypes.c_int32),
+                ("lanes", ctypes.c_int32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -229,23 +231,24 @@ class Context:
             pass
 
     # -- tile shapes ---------------------------------------------------------
-    def set_tile(self, cols_per_lane: int = 0, rows: int = 0):
-        t = Tile(int(cols_per_lane), int(rows))
+    def set_tile(self, cols_per_lane: int = 0, rows: int = 0, lanes: int = 64):
+        t = Tile(int(cols_per_lane), int(rows), int(lanes))
         check("sne_set_tile", lib().sne_set_tile(self._h, ctypes.byref(t)))
 
-    def get_tile(self, H, W, kind="depth_f32", grad="fd", agg="mean", out="f32") -> Tuple[int, int]:
+    def get_tile(self, H, W, kind="depth_f32", grad="fd", agg="mean",
+                 out="f32") -> Tuple[int, int, int]:
         t = Tile()
         check("sne_get_tile", lib().sne_get_tile(self._h, H, W, _enum(KIND, kind, "kind"),
                                                  _enum(GRAD, grad, "grad"), _enum(AGG, agg, "agg"),
                                                  _enum(OUT, out, "out"), ctypes.byref(t)))
-        return t.cols_per_lane, t.rows
+        return t.cols_per_lane, t.rows, t.lanes
 
     def autotune(self, H, W, B=1, kind="depth_f32", grad="fd", agg="mean", out="f32"):
         t = Tile()
         check("sne_autotune", lib().sne_autotune(self._h, H, W, B, _enum(KIND, kind, "kind"),
                                                  _enum(GRAD, grad, "grad"), _enum(AGG, agg, "agg"),
                                                  _enum(OUT, out, "out"), ctypes.byref(t)))
-        return t.cols_per_lane, t.rows
+        return t.cols_per_lane, t.rows, t.lanes
 
     def autotune_save(self, path: str):
         check("sne_autotune_save", lib().sne_autotune_save(self._h, path.encode()))

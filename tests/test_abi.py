@@ -80,9 +80,9 @@ def test_default_tile_shape_without_context():
     L = sne.lib()
     t = sne.Tile()
     assert L.sne_get_tile(None, 480, 640, 0, 0, 0, 0, ctypes.byref(t)) == 0
-    assert t.cols_per_lane in (1, 2, 4) and 1 <= t.rows <= 1024
-    # 640 = 5 x 128: two columns per lane leaves no idle lane
-    assert t.cols_per_lane == 2
+    assert t.cols_per_lane in (1, 2, 4) and 1 <= t.rows <= 1024 and t.lanes in (32, 64)
+    # 640 = 5 x 128: the chosen strip width leaves no idle lane
+    assert 640 % (t.cols_per_lane * t.lanes) == 0
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):

@@ -108,21 +108,23 @@ def test_f16_depth(agg):
 
 # ---------------------------------------------------------------- tile shapes
 
+@pytest.mark.parametrize("lanes", [64, 32])
 @pytest.mark.parametrize("px", [1, 2, 4])
 @pytest.mark.parametrize("rows", [1, 3, 16])
-def test_tile_shapes_ragged(px, rows):
+def test_tile_shapes_ragged(px, rows, lanes):
     """A frame that spans several tiles with ragged right and bottom edges;
-    every tile shape gives bit-identical output that matches the oracle."""
+    every tile shape, full- or half-wave, gives bit-identical output that
+    matches the oracle."""
     cam = S.Camera(150, 200, 150.4, 150.4, 99.5, 74.5)
     fr = S.make_cluttered(1002, cam)
     raw = fr.raw.numpy()
     ctx = sne.Context(0)
-    ctx.set_tile(px, rows)
+    ctx.set_tile(px, rows, lanes)
     results = []
     for grad, agg in [("fd", "mean"), ("scharr", "median")]:
         gn, gm = gpu_estimate(raw, cam.as_tuple(), "depth_f32", grad, agg, ctx=ctx)
         on, om = oracle.estimate(raw, "depth_f32", k32(cam.as_tuple()), grad, agg)
-        check_parity(gn, gm, on, om, label="tile %dx%d %s-%s" % (px, rows, grad, agg))
+        check_parity(gn, gm, on, om, label="tile %dx%dx%d %s-%s" % (px, rows, lanes, grad, agg))
         results.append(gn)
     ref = sne.Context(0)
     ref.set_tile(1, 8)
@@ -272,7 +274,7 @@ def test_uniform_batch_equals_single_bitwise():
         check_parity(nb[3].double().cpu().numpy(), mb[3].cpu().numpy(), on, om, label="uniform")
 
 
-@pytest.mark.parametrize("px_rows", [None, (1, 5), (4, 32)])
+@pytest.mark.parametrize("px_rows", [None, (1, 5), (4, 32), (4, 7, 32), (2, 16, 32)])
 def test_uneven_persistent_batch_equals_single_bitwise(px_rows):
     shapes = [(240, 320), (48, 64), (100, 128), (240, 320), (72, 96), (33, 64)]
     cams = [S.camera_for(h, w) for h, w in shapes]
