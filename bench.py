@@ -110,10 +110,11 @@ def copy_calibration(torch, nbytes=1 << 30, reps=10):
             "us_per_copy": round(ev / reps * 1e6, 1)}
 
 
-def uneven_batch(torch, S, sne, agg, n_frames=1024, reps=5):
+def uneven_batch(torch, S, sne, agg, n_frames=1024, reps=5, autotune=False):
     """One persistent launch over n_frames frames of sizes drawn uniformly
     from {240x320, 480x640, 720x1280, 1080x1920}: uint16 millimetre depth in,
-    FP16 normals + mask out (9 B/px), FD gradients, autotuned tile shape."""
+    FP16 normals + mask out (9 B/px), FD gradients, tile shape from the
+    shipped tuning table (or tuned live)."""
     shapes = S.uneven_sizes(n_frames, seed=3999)
     uniq = sorted(set(shapes))
     ctx = sne.Context(0)
@@ -126,7 +127,8 @@ def uneven_batch(torch, S, sne, agg, n_frames=1024, reps=5):
     frames = [pool[sh][k % 16] for k, sh in enumerate(shapes)]
     nrm = [torch.empty((3,) + sh, dtype=torch.float16, device="cuda") for sh in shapes]
     msk = [torch.empty(sh, dtype=torch.uint8, device="cuda") for sh in shapes]
-    ctx.autotune(1080, 1920, 64, "depth_u16", "fd", agg, "f16")
+    if autotune:
+        ctx.autotune(1080, 1920, 64, "depth_u16", "fd", agg, "f16")
     ki = [kidx[sh] for sh in shapes]
     descs, _, _ = ctx.prepare_batched(frames, ki, "depth_u16", "f16", nrm, msk)
     wall, ev = time_launches(torch, lambda i: ctx.run_batched(descs, "depth_u16", "fd", agg, "f16"),
@@ -213,7 +215,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the tile shape live instead of using the shipped table")
     ap.add_argument("--tile", default="",
                     help="force cols_per_lane,rows[,lanes] (skips autotuning)")
     args = ap.parse_args()
@@ -246,10 +249,10 @@ def main():
     if args.tile:
         tile = tuple(int(x) for x in args.tile.split(","))
         ctx.set_tile(*tile)
-        tile = ctx.get_tile(H, W, "depth_f32", args.grad, args.agg, "f32")
-    elif not args.no_autotune:
+    elif args.autotune:
         log("autotuning the tile shape")
-        tile = ctx.autotune(H, W, B, "depth_f32", args.grad, args.agg, "f32")
+        ctx.autotune(H, W, B, "depth_f32", args.grad, args.agg, "f32")
+    tile = ctx.get_tile(H, W, B, "depth_f32", args.grad, args.agg, "f32")
 
     def step(i):
         raw, nrm, msk = bufs[i % NBUF]

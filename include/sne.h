@@ -160,9 +160,10 @@ typedef struct {
  * back to a narrower cols_per_lane. */
 int sne_set_tile(sne_ctx *ctx, const sne_tile *tile);
 
-/* The tile shape ctx would use for an H x W frame of this variant. */
-int sne_get_tile(sne_ctx *ctx, int32_t H, int32_t W, int kind, int grad, int agg, int out_type,
-                 sne_tile *tile);
+/* The tile shape ctx would use for a batch of B frames of H x W of this
+ * variant (ctx may be NULL: the built-in heuristic). */
+int sne_get_tile(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int grad, int agg,
+                 int out_type, sne_tile *tile);
 
 /* Time every candidate tile shape on an H x W x B workload of this variant
  * (synthetic planar input in scratch buffers the call allocates and frees),

@@ -8,7 +8,7 @@
 #include <string>
 #include <tuple>
 
-#include "../../include/sne.h"
+#include "sne.h"
 #include "sne_internal.h"
 
 namespace sne {
@@ -52,7 +52,18 @@ struct Slot {
 bool valid_enum(int kind, int grad, int agg, int out);
 bool valid_K(const sne_intrinsics *K, int kind);
 size_t in_elem(int kind);
-size_t out_elem(int out);
+size_t out_elem(int out_type);
+
+// The kernels address one frame with 32-bit byte offsets: the input (with a
+// row of margin above and below) below 2^31, each output plane and the mask
+// below 2^32.
+inline bool frame_fits(int64_t H, int64_t in_pitch, int kind, int64_t out_pitch, int out_type,
+                       int64_t mask_pitch) {
+    return (H + 2) * in_pitch * (int64_t)in_elem(kind) < INT32_MAX &&
+           H * out_pitch * (int64_t)out_elem(out_type) <= (int64_t)UINT32_MAX &&
+           H * mask_pitch <= (int64_t)UINT32_MAX;
+}
+
 void grad_weights(int grad, float &wa, float &wb);
 int max_px(const void *in, const void *out, const uint8_t *mask, int W, int64_t in_pitch,
            int64_t out_pitch, int64_t mask_pitch, int64_t in_fs, int64_t out_fs, int64_t mask_fs,

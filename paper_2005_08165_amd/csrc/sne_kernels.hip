@@ -42,6 +42,17 @@
 #endif
 
 // Rows loaded ahead of the row being finished (1 or 2).
+// Minimum wavefronts per SIMD the register allocator has to leave room for
+// (0: the compiler's choice).
+#ifndef SNE_WAVES_PER_EU
+#define SNE_WAVES_PER_EU 0
+#endif
+#if SNE_WAVES_PER_EU > 0
+#define SNE_OCCUPANCY __attribute__((amdgpu_waves_per_eu(SNE_WAVES_PER_EU)))
+#else
+#define SNE_OCCUPANCY
+#endif
+
 #ifndef SNE_PREFETCH_ROWS
 #define SNE_PREFETCH_ROWS 1
 #endif
@@ -50,7 +61,9 @@ namespace sne {
 namespace {
 
 constexpr float kInf = __builtin_huge_valf();
-constexpr float kFltMax = 3.40282347e38f;
+// class-test mask (v_cmp_class) of the positive finite non-zero values:
+// +denormal | +normal, i.e. 0 < x <= FLT_MAX
+constexpr int kPosFinite = (1 << 7) | (1 << 8);
 
 // lane l receives lane l-1's `src`; lane 0 (no source) keeps `old`.
 __device__ __forceinline__ float from_left(float old, float src) {
@@ -115,7 +128,7 @@ __device__ __forceinline__ float vmax3(float a, float b, float c) {
 template <int KIND> struct Raw;
 template <> struct Raw<KIND_F32> {
     using T = float;
-    __device__ static float value(T x) { return (x > 0.f && x <= kFltMax) ? x : 0.f; }
+    __device__ static float value(T x) { return __builtin_amdgcn_classf(x, kPosFinite) ? x : 0.f; }
 };
 template <> struct Raw<KIND_DISP> : Raw<KIND_F32> {};
 template <> struct Raw<KIND_U16> {
@@ -126,7 +139,7 @@ template <> struct Raw<KIND_F16> {
     using T = uint16_t;  // binary16 bits
     __device__ static float value(T x) {
         const float f = (float)__builtin_bit_cast(_Float16, x);
-        return (f > 0.f && f <= kFltMax) ? f : 0.f;
+        return __builtin_amdgcn_classf(f, kPosFinite) ? f : 0.f;
     }
 };
 
@@ -153,7 +166,12 @@ __device__ __forceinline__ InBuf make_inbuf(const void *base, int64_t pitch, int
     return b;
 }
 
-constexpr int kOOB = 0x7fffffff;  // a byte offset past any frame
+// Column offset of a lane that loads nothing.  With the frame's input below
+// 2^31 - 2 pitches (checked by the host), kOOB + r * pitch for the rows
+// -1 <= r <= H + 1 lands at or past the end of the buffer, as does any
+// in-frame column at row -1 (the offset wraps past 2^31); further rows never
+// feed a stored output.
+constexpr int kOOB = 0x7fffffff;
 
 template <typename T, int N> __device__ __forceinline__ Vec<T, N> buf_load(const InBuf &b, int off);
 template <> __device__ __forceinline__ Vec<float, 1> buf_load<float, 1>(const InBuf &b, int off) {
@@ -182,9 +200,9 @@ template <int KIND, int PX>
 __device__ __forceinline__ void load_raw(const InBuf &b, int r, int col_off, int halo_off,
                                          RawRow<KIND, PX> &o) {
     using T = typename Raw<KIND>::T;
-    const int row = r * b.pitch_bytes;  // negative or past the end -> out of range
-    o.x = buf_load<T, PX>(b, col_off == kOOB ? kOOB : row + col_off);
-    o.h = buf_load<T, 1>(b, halo_off == kOOB ? kOOB : row + halo_off).v[0];
+    const unsigned row = (unsigned)r * (unsigned)b.pitch_bytes;  // wraps for r = -1
+    o.x = buf_load<T, PX>(b, (int)(row + (unsigned)col_off));
+    o.h = buf_load<T, 1>(b, (int)(row + (unsigned)halo_off)).v[0];
 }
 
 // Per-row state.  Index i of z/s is column (lane base + i - 1): 0 and PX+1
@@ -407,6 +425,28 @@ __device__ __forceinline__ float mean8(const float (&Nj)[8], const float (&rj)[8
     return sum * rcp((float)m);
 }
 
+// Outputs are written once and not read back by this kernel: nontemporal
+// stores keep them from displacing the input rows that neighbouring tiles
+// still read from the caches.
+template <typename V> __device__ __forceinline__ void store_stream(void *p, const V &v) {
+    if constexpr (sizeof(V) == 16) {
+        typedef unsigned U __attribute__((ext_vector_type(4)));
+        __builtin_nontemporal_store(__builtin_bit_cast(U, v), static_cast<U *>(p));
+    } else if constexpr (sizeof(V) == 8) {
+        typedef unsigned U __attribute__((ext_vector_type(2)));
+        __builtin_nontemporal_store(__builtin_bit_cast(U, v), static_cast<U *>(p));
+    } else if constexpr (sizeof(V) == 4) {
+        __builtin_nontemporal_store(__builtin_bit_cast(unsigned, v), static_cast<unsigned *>(p));
+    } else if constexpr (sizeof(V) == 2) {
+        __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, v),
+                                    static_cast<unsigned short *>(p));
+    } else {
+        static_assert(sizeof(V) == 1, "store width");
+        __builtin_nontemporal_store(__builtin_bit_cast(unsigned char, v),
+                                    static_cast<unsigned char *>(p));
+    }
+}
+
 // Output row r of a tile from the window (prev, cur, next); `pend` holds the
 // raw loads of row r + 1 on entry and those of row r + 1 + SNE_PREFETCH_ROWS
 // on exit.
@@ -486,16 +526,19 @@ __device__ __forceinline__ void tile_row(const FrameDesc &f, const InBuf &ib, in
         mk[k] = valid ? 1 : 0;
     }
     if (col < f.W && r < rend) {
-        OT *o = static_cast<OT *>(f.out) + (int64_t)r * f.out_pitch + col;
-        *reinterpret_cast<Vec<OT, PX> *>(o) = ox;
-        *reinterpret_cast<Vec<OT, PX> *>(o + f.out_plane) = oy;
-        *reinterpret_cast<Vec<OT, PX> *>(o + 2 * f.out_plane) = oz;
+        // uniform plane bases + one 32-bit byte offset per lane (the host
+        // keeps each plane below 4 GiB)
+        char *o = static_cast<char *>(f.out);
+        const int64_t plane = f.out_plane * (int64_t)sizeof(OT);
+        const unsigned off = ((unsigned)r * (unsigned)f.out_pitch + (unsigned)col) * sizeof(OT);
+        store_stream(o + off, ox);
+        store_stream(o + plane + off, oy);
+        store_stream(o + 2 * plane + off, oz);
         if (f.mask) {
             typename MaskWord<PX>::T w = 0;
 #pragma unroll
             for (int k = 0; k < PX; ++k) w |= (typename MaskWord<PX>::T)mk[k] << (8 * k);
-            *reinterpret_cast<typename MaskWord<PX>::T *>(f.mask + (int64_t)r * f.mask_pitch +
-                                                          col) = w;
+            store_stream(f.mask + ((unsigned)r * (unsigned)f.mask_pitch + (unsigned)col), w);
         }
     }
 }
@@ -577,7 +620,7 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 }
 
 template <int KIND, bool FD, int AGG, int OUT, int PX, bool HALF>
-__global__ __launch_bounds__(kBlock) void sne_uniform_kernel(UniformArgs a) {
+__global__ __launch_bounds__(kBlock) SNE_OCCUPANCY void sne_uniform_kernel(UniformArgs a) {
     const int b = a.xcd_remap ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     // wave-uniform by construction; readfirstlane lets the compiler keep the
     // frame's buffer resource in scalar registers
@@ -603,7 +646,7 @@ __global__ __launch_bounds__(kBlock) void sne_uniform_kernel(UniformArgs a) {
 // Persistent uneven batch: every wavefront pulls `chunk` consecutive tiles at
 // a time from a device counter until the queue is drained.
 template <int KIND, bool FD, int AGG, int OUT, int PX, bool HALF>
-__global__ __launch_bounds__(kBlock) void sne_batch_kernel(BatchArgs a) {
+__global__ __launch_bounds__(kBlock) SNE_OCCUPANCY void sne_batch_kernel(BatchArgs a) {
     const int lane = threadIdx.x & (kWave - 1);
     const int nframes = a.counts ? a.counts[0] : a.nframes;
     const int ntiles = a.counts ? a.counts[1] : a.ntiles;

@@ -340,7 +340,7 @@ int sne_server_submit(sne_server *srv, const sne_request *req, uint64_t *ticket)
         req->reserved != 0)
         return SNE_ERR_ARG;
     if (req->stream_id < 0 || req->stream_id >= srv->ctx->nK) return SNE_ERR_ARG;
-    if ((int64_t)(req->H + 2) * req->in_pitch * (int64_t)in_elem(srv->cfg.kind) >= INT32_MAX)
+    if (!frame_fits(req->H, req->in_pitch, srv->cfg.kind, req->W, srv->cfg.out_type, req->W))
         return SNE_ERR_UNSUPPORTED;
     Payload *p = new Payload{req->in, req->in_pitch};
     sched::Request r;

@@ -19,6 +19,7 @@ import torch
 PKG = os.path.dirname(os.path.abspath(__file__))
 # SNE_LIBRARY selects another build of the same library (e.g. an experiment)
 LIB_PATH = os.environ.get("SNE_LIBRARY", os.path.join(PKG, "libsne.so"))
+TUNING_TABLE = os.path.join(PKG, "tuning.txt")  # written by paper_2005_08165_amd.tune
 HEADER = os.path.join(os.path.dirname(PKG), "include", "sne.h")
 
 SNE_OK = 0
@@ -129,7 +130,7 @@ _SIGS = {
     "sne_estimate_batched": ([_vp, ctypes.POINTER(FrameDesc), _i32, _int, _int, _int, _int, _vp],
                              _int),
     "sne_set_tile": ([_vp, ctypes.POINTER(Tile)], _int),
-    "sne_get_tile": ([_vp, _i32, _i32, _int, _int, _int, _int, ctypes.POINTER(Tile)], _int),
+    "sne_get_tile": ([_vp, _i32, _i32, _i32, _int, _int, _int, _int, ctypes.POINTER(Tile)], _int),
     "sne_autotune": ([_vp, _i32, _i32, _i32, _int, _int, _int, _int, ctypes.POINTER(Tile)], _int),
     "sne_autotune_save": ([_vp, ctypes.c_char_p], _int),
     "sne_autotune_load": ([_vp, ctypes.c_char_p], _int),
@@ -210,10 +211,14 @@ def _row_pitch(t: torch.Tensor) -> int:
 class Context:
     """Owns an sne_ctx bound to one GPU."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, tuning: bool = True):
+        """`tuning`: load the shipped tile table (tuning.txt beside this
+        module) when it exists; without it tiles come from the heuristic."""
         self._h = ctypes.c_void_p()
         check("sne_ctx_create", lib().sne_ctx_create(ctypes.byref(self._h), int(device)))
         self.device = int(device)
+        if tuning and os.path.exists(TUNING_TABLE):
+            self.autotune_load(TUNING_TABLE)
 
     @property
     def handle(self):
@@ -235,10 +240,10 @@ class Context:
         t = Tile(int(cols_per_lane), int(rows), int(lanes))
         check("sne_set_tile", lib().sne_set_tile(self._h, ctypes.byref(t)))
 
-    def get_tile(self, H, W, kind="depth_f32", grad="fd", agg="mean",
+    def get_tile(self, H, W, B=1, kind="depth_f32", grad="fd", agg="mean",
                  out="f32") -> Tuple[int, int, int]:
         t = Tile()
-        check("sne_get_tile", lib().sne_get_tile(self._h, H, W, _enum(KIND, kind, "kind"),
+        check("sne_get_tile", lib().sne_get_tile(self._h, H, W, B, _enum(KIND, kind, "kind"),
                                                  _enum(GRAD, grad, "grad"), _enum(AGG, agg, "agg"),
                                                  _enum(OUT, out, "out"), ctypes.byref(t)))
         return t.cols_per_lane, t.rows, t.lanes

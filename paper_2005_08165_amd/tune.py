@@ -1,0 +1,46 @@
+"""Offline tile tuning for the shipped tuning table.
+
+    python -m paper_2005_08165_amd.tune [--out FILE]
+
+Runs the library's autotuner (sne_autotune) on each standard workload below
+and writes the resulting table (sne_autotune_save format).  A Context loads
+the shipped table, ``tuning.txt`` beside this file, when it is created; lines
+for other GPU architectures or library versions are ignored.
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+
+from . import sne
+
+TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.txt")
+
+# (H, W, batch, input kind, gradient filter, aggregation, output type)
+WORKLOADS = [
+    (480, 640, 64, "depth_f32", "sobel", "median", "f32"),
+    (480, 640, 64, "depth_f32", "fd", "mean", "f32"),
+    (480, 640, 1, "depth_f32", "sobel", "median", "f32"),
+    (375, 1242, 128, "disparity_f32", "sobel", "median", "f32"),
+    (1080, 1920, 64, "depth_u16", "fd", "median", "f16"),
+    (1080, 1920, 1, "depth_u16", "fd", "median", "f16"),
+]
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=TABLE)
+    args = ap.parse_args(argv)
+    ctx = sne.Context(0, tuning=False)
+    for H, W, B, kind, grad, agg, out in WORKLOADS:
+        t = ctx.autotune(H, W, B, kind, grad, agg, out)
+        print("%dx%d B=%d %s %s-%s %s -> cols_per_lane %d rows %d lanes %d"
+              % (H, W, B, kind, grad, agg, out, *t), flush=True)
+    ctx.autotune_save(args.out)
+    print(args.out)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,6 +1,7 @@
 """The C ABI library loads, exports what include/sne.h declares, and rejects
 bad arguments with status codes before touching the GPU."""
 import ctypes
+import os
 
 import pytest
 
@@ -73,13 +74,14 @@ def test_null_context_errors():
     assert L.sne_autotune_save(None, b"/tmp/x") == -1
     assert L.sne_ctx_destroy(None) == 0
     assert L.sne_ctx_create(None, 0) == -1
-    assert L.sne_get_tile(None, 0, 10, 0, 0, 0, 0, ctypes.byref(t)) == -1
+    assert L.sne_get_tile(None, 0, 10, 1, 0, 0, 0, 0, ctypes.byref(t)) == -1
+    assert L.sne_get_tile(None, 10, 10, 0, 0, 0, 0, 0, ctypes.byref(t)) == -1
 
 
 def test_default_tile_shape_without_context():
     L = sne.lib()
     t = sne.Tile()
-    assert L.sne_get_tile(None, 480, 640, 0, 0, 0, 0, ctypes.byref(t)) == 0
+    assert L.sne_get_tile(None, 480, 640, 64, 0, 0, 0, 0, ctypes.byref(t)) == 0
     assert t.cols_per_lane in (1, 2, 4) and 1 <= t.rows <= 1024 and t.lanes in (32, 64)
     # 640 = 5 x 128: the chosen strip width leaves no idle lane
     assert 640 % (t.cols_per_lane * t.lanes) == 0
@@ -90,3 +92,25 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(sne, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="not built"):
         sne.lib()
+
+
+def test_shipped_tuning_table_is_well_formed():
+    """Every line of the shipped tile table parses as sne_autotune_save
+    writes it, with shapes the library accepts; the batched 480x640
+    Sobel-median workload has an entry."""
+    from paper_2005_08165_amd import tune
+    assert os.path.exists(sne.TUNING_TABLE) and sne.TUNING_TABLE == tune.TABLE
+    keys = set()
+    for line in open(sne.TUNING_TABLE):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        assert len(f) == 13, line
+        arch, ver, H, W, bc, kind, grad, agg, out, px, rows, remap, half = (
+            [f[0]] + [int(x) for x in f[1:]])
+        assert ver == sne.version() and H >= 1 and W >= 1 and bc in (0, 1, 2)
+        assert kind in sne.KIND.values() and grad in sne.GRAD.values()
+        assert agg in sne.AGG.values() and out in (0, 1)
+        assert px in (1, 2, 4) and 1 <= rows <= 1024 and remap in (0, 1) and half in (0, 1)
+        keys.add((H, W, bc, kind, grad, agg, out))
+    assert (480, 640, 2, 0, 1, 1, 0) in keys

@@ -297,6 +297,34 @@ def test_uneven_persistent_batch_equals_single_bitwise(px_rows):
                      label="uneven")
 
 
+def test_autotune_and_tuning_table():
+    """The autotuner returns a valid shape that the context then uses; a
+    context created with the shipped table reports the table's entry for the
+    batched 480x640 workload; all of them give the same output bitwise."""
+    ctx = sne.Context(0, tuning=False)
+    t = ctx.autotune(120, 160, 4, "depth_f32", "sobel", "median", "f32")
+    assert t[0] in (1, 2, 4) and 1 <= t[1] <= 1024 and t[2] in (32, 64)
+    assert ctx.get_tile(120, 160, 4, "depth_f32", "sobel", "median", "f32") == t
+    shipped = sne.Context(0)
+    want = None
+    for line in open(sne.TUNING_TABLE):
+        f = line.split()
+        if len(f) == 13 and [int(x) for x in f[2:9]] == [480, 640, 2, 0, 1, 1, 0]:
+            if f[0] == torch.cuda.get_device_properties(0).gcnArchName:
+                want = (int(f[9]), int(f[10]), 32 if int(f[12]) else 64)
+    if want is not None:
+        assert shipped.get_tile(480, 640, 64, "depth_f32", "sobel", "median", "f32") == want
+    cam = S.Camera(120, 160, 120.2, 120.2, 79.5, 59.5)
+    raw = torch.stack([S.make_cluttered(1100 + i, cam, device="cuda").raw for i in range(4)])
+    outs = []
+    for c in (ctx, shipped, sne.Context(0, tuning=False)):
+        n, m = sne.estimate_uniform(raw, cam.as_tuple(), "depth_f32", "sobel", "median", ctx=c)
+        outs.append((n, m))
+    torch.cuda.synchronize()
+    for n, m in outs[1:]:
+        assert torch.equal(n, outs[0][0]) and torch.equal(m, outs[0][1])
+
+
 def test_determinism():
     fr = S.make_cluttered(1004)
     raw = fr.raw.cuda()
@@ -373,8 +401,8 @@ def test_full_size_disparity_batch128():
 
 def test_full_size_uneven_1024_persistent():
     """1024 frames of sizes drawn from {240x320 .. 1080x1920}, uint16 mm depth,
-    FD-median, FP16 out, one persistent launch with the autotuned tile (the
-    configuration the benchmark times).  Sampled pixels of several frames of
+    FD-median, FP16 out, one persistent launch with the tile of the shipped
+    tuning table (the configuration the benchmark times).  Sampled pixels of several frames of
     every size against the oracle, plus the per-pixel properties."""
     shapes = S.uneven_sizes(1024, seed=3999)
     uniq = sorted(set(shapes))
@@ -386,7 +414,6 @@ def test_full_size_uneven_1024_persistent():
     pool = {sh: [S.make_u16(4000 + 97 * j + i, cams[sh], device="cuda").raw for j in range(4)]
             for i, sh in enumerate(uniq)}
     frames = [pool[sh][k % 4] for k, sh in enumerate(shapes)]
-    ctx.autotune(1080, 1920, 64, "depth_u16", "fd", "median", "f16")
     normals, masks = ctx.estimate_batched(frames, [kidx[sh] for sh in shapes], "depth_u16", "fd",
                                           "median", "f16")
     torch.cuda.synchronize()
