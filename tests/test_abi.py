@@ -114,3 +114,23 @@ def test_shipped_tuning_table_is_well_formed():
         assert px in (1, 2, 4) and 1 <= rows <= 1024 and remap in (0, 1) and half in (0, 1)
         keys.add((H, W, bc, kind, grad, agg, out))
     assert (480, 640, 2, 0, 1, 1, 0) in keys
+
+
+def test_frames_past_the_32bit_offset_limits_are_rejected():
+    """The kernels address a frame with 32-bit byte offsets: the input (with
+    a row of margin above and below) must stay below 2^31 bytes, each output
+    plane and the mask below 4 GiB.  Larger frames return
+    SNE_ERR_UNSUPPORTED before anything is launched (fake pointers here)."""
+    L = sne.lib()
+    K = _K()
+
+    def est(H, W, in_pitch, kind, out, out_pitch, mask_pitch):
+        return L.sne_estimate(None, FAKE, H, W, in_pitch, ctypes.byref(K), kind, 1, 1, out, FAKE,
+                              out_pitch, FAKE, mask_pitch, None)
+
+    W = 32760
+    assert (16386 + 2) * W * 4 < 2 ** 31 - 1 < (16387 + 2) * W * 4
+    assert est(16387, W, W, 0, 0, W, W) == -2          # FP32 input one row too tall
+    assert est(2 * 16387 + 1, W, W, 1, 1, W, W) == -2  # u16 input: twice the rows + 1
+    assert est(1024, 1000, 1000, 0, 0, 1 << 20, 1000) == -2   # output plane = 4 GiB
+    assert est(1024, 1000, 1000, 0, 0, 1000, 1 << 22) == -2   # mask = 4 GiB

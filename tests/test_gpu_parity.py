@@ -399,6 +399,39 @@ def test_full_size_disparity_batch128():
                     20000, 2, tc=S.ROAD_BASELINE)
 
 
+def test_maximum_frame_size():
+    """The tallest FP32 frame of width 32760 the boundary accepts:
+    (H + 2) x pitch x 4 B just below 2^31 (one more row is rejected, see the
+    C ABI tests), 537 Mpx in one launch.  Sampled pixels against the oracle,
+    properties on every pixel."""
+    H, W = 16386, 32760
+    assert (H + 2) * W * 4 < 2 ** 31 - 1 < (H + 3) * W * 4
+    cam = S.camera_for(H, W)
+    say("rendering a %dx%d frame" % (H, W))
+    raw = S.make_cluttered(1200, cam, device="cuda").raw.unsqueeze(0)
+    torch.cuda.synchronize()
+    n, m = sne.estimate_uniform(raw, cam.as_tuple(), "depth_f32", "sobel", "median")
+    torch.cuda.synchronize()
+    say("checking")
+    _sampled_parity(raw, n, m, cam.as_tuple(), "depth_f32", "sobel", "median", "f32", 1, 50000, 7)
+    # the last rows and columns, where the offsets are largest
+    rng = np.random.default_rng(8)
+    pix = np.concatenate([(H - 1 - rng.integers(0, 3, 2000)) * W + rng.integers(0, W, 2000),
+                          rng.integers(0, H, 2000) * W + (W - 1 - rng.integers(0, 3, 2000))])
+    host = raw[0].cpu().numpy()
+    on, om = oracle.estimate_pixels(host, "depth_f32", k32(cam.as_tuple()), pix, "sobel", "median")
+    idx = torch.from_numpy(pix).cuda()
+    g = n[0].reshape(3, -1)[:, idx].double().cpu().numpy()
+    gm = m[0].reshape(-1)[idx].cpu().numpy()
+    assert (gm == om).all()
+    v = om.astype(bool)
+    assert v.sum() > 1000
+    e = oracle.angular_error_deg(g[:, v], on[v].T)
+    assert e.mean() <= TOL["f32"][0] and e.max() <= TOL["f32"][1]
+    del raw, n, m
+    torch.cuda.empty_cache()
+
+
 def test_full_size_uneven_1024_persistent():
     """1024 frames of sizes drawn from {240x320 .. 1080x1920}, uint16 mm depth,
     FD-median, FP16 out, one persistent launch with the tile of the shipped
