@@ -53,6 +53,18 @@
 #define SNE_OCCUPANCY
 #endif
 
+// The persistent kernel keeps the tile loop's state live across tiles and
+// would otherwise exceed 128 registers at 4 columns per lane (3 wavefronts
+// per SIMD); holding it to 4 costs a few spilled dwords and is faster.
+#ifndef SNE_BATCH_WAVES_PER_EU
+#define SNE_BATCH_WAVES_PER_EU 4
+#endif
+#if SNE_BATCH_WAVES_PER_EU > 0
+#define SNE_BATCH_OCCUPANCY __attribute__((amdgpu_waves_per_eu(SNE_BATCH_WAVES_PER_EU)))
+#else
+#define SNE_BATCH_OCCUPANCY
+#endif
+
 #ifndef SNE_PREFETCH_ROWS
 #define SNE_PREFETCH_ROWS 1
 #endif
@@ -646,7 +658,7 @@ __global__ __launch_bounds__(kBlock) SNE_OCCUPANCY void sne_uniform_kernel(Unifo
 // Persistent uneven batch: every wavefront pulls `chunk` consecutive tiles at
 // a time from a device counter until the queue is drained.
 template <int KIND, bool FD, int AGG, int OUT, int PX, bool HALF>
-__global__ __launch_bounds__(kBlock) SNE_OCCUPANCY void sne_batch_kernel(BatchArgs a) {
+__global__ __launch_bounds__(kBlock) SNE_BATCH_OCCUPANCY void sne_batch_kernel(BatchArgs a) {
     const int lane = threadIdx.x & (kWave - 1);
     const int nframes = a.counts ? a.counts[0] : a.nframes;
     const int ntiles = a.counts ? a.counts[1] : a.ntiles;
