@@ -144,11 +144,16 @@ def uneven_batch(torch, S, sne, agg, n_frames=1024, reps=5, autotune=False):
             "note": "event time per call: descriptor staging copy + counter reset + kernel"}
 
 
-def serving(torch, S, sne, rates=(20000, 60000, 120000), duration=2.0):
+def serving(torch, S, sne, duration=2.0, slo_p99_ms=2.0,
+            plan=(("mean", (20000, 60000, 100000, 120000, 140000, 160000)),
+                  ("median", (20000, 60000, 100000, 120000, 140000)))):
     """64 sensor streams (resolution per stream drawn with seed 5001 from
     {240x320 .. 2160x3840}), Poisson arrivals (seed 5000), uint16 depth in a
     device-resident ring of 2 frames per stream, per-stream intrinsics on the
-    device, FP16 normals, FD-mean; continuous batching with hipGraph replay."""
+    device, FP16 normals, FD-mean and FD-median; continuous batching with
+    hipGraph replay.  The offered rate rises until the p99 latency passes
+    slo_p99_ms (saturation sweep).  Host-to-device ingest over PCIe is
+    measured separately: the rings stand in for sensor DMA into HBM."""
     import numpy as np
     shapes_all = [(240, 320), (480, 640), (720, 1280), (1080, 1920), (2160, 3840)]
     rng = np.random.default_rng(5001)
@@ -159,23 +164,44 @@ def serving(torch, S, sne, rates=(20000, 60000, 120000), duration=2.0):
     rings = [[S.make_u16(5100 + 2 * s + k, cams[s], device="cuda").raw for k in range(2)]
              for s in range(64)]
     torch.cuda.synchronize()
-    srv = sne.Server(ctx, "depth_u16", "fd", "mean", "f16", max_inflight=3,
-                     max_batch_frames=256, hbm_budget_bytes=16 << 30, use_graphs=True)
-    out = {"streams": 64, "mean_mpix_per_frame": round(np.mean([h * w for h, w in shapes]) / 1e6, 3),
-           "runs": []}
-    for lam in rates:
-        log("serving at %d frames/s" % lam)
-        st = srv.run_open_loop(rings, total_rate=lam, duration_s=duration, seed=5000,
-                               n_producers=8)
-        out["runs"].append({"offered_fps": lam, "completed": st["completed"],
-                            "p50_ms": round(st["latency_p50"] * 1e3, 3),
-                            "p99_ms": round(st["latency_p99"] * 1e3, 3),
-                            "p999_ms": round(st["latency_p999"] * 1e3, 3),
-                            "mpix_per_s": round(st["mpix_per_s"], 1),
-                            "frames_per_s": round(st["frames_per_s"], 1),
-                            "mean_batch_frames": round(st["mean_batch_frames"], 2),
-                            "hbm_GBs_algorithmic": round(st["mpix_per_s"] * 9 / 1e3, 1)})
-    srv.close()
+    mean_px = float(np.mean([h * w for h, w in shapes]))
+    out = {"streams": 64, "mean_mpix_per_frame": round(mean_px / 1e6, 3),
+           "slo_p99_ms": slo_p99_ms, "runs": []}
+    for agg, rates in plan:
+        srv = sne.Server(ctx, "depth_u16", "fd", agg, "f16", max_inflight=3,
+                         max_batch_frames=256, hbm_budget_bytes=16 << 30, use_graphs=True)
+        for lam in rates:
+            log("serving FD-%s at %d frames/s" % (agg, lam))
+            st = srv.run_open_loop(rings, total_rate=lam, duration_s=duration, seed=5000,
+                                   n_producers=8)
+            p99 = st["latency_p99"] * 1e3
+            out["runs"].append({"agg": agg, "offered_fps": lam, "completed": st["completed"],
+                                "p50_ms": round(st["latency_p50"] * 1e3, 3),
+                                "p99_ms": round(p99, 3),
+                                "p999_ms": round(st["latency_p999"] * 1e3, 3),
+                                "mpix_per_s": round(st["mpix_per_s"], 1),
+                                "frames_per_s": round(st["frames_per_s"], 1),
+                                "mean_batch_frames": round(st["mean_batch_frames"], 2),
+                                "hbm_GBs_algorithmic": round(st["mpix_per_s"] * 9 / 1e3, 1),
+                                "meets_slo": p99 <= slo_p99_ms})
+            if p99 > slo_p99_ms:
+                break
+        srv.close()
+    # PCIe ingest: pinned host -> device copies of 256 MB
+    host = torch.empty(256 << 20, dtype=torch.uint8, pin_memory=True)
+    dev = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    for _ in range(2):
+        dev.copy_(host, non_blocking=True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dev.copy_(host, non_blocking=True)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 10 * (256 << 20) / (e0.elapsed_time(e1) / 1e3) / 1e9
+    out["pcie_h2d_GBs"] = round(gbs, 1)
+    out["pcie_ingest_bound_fps"] = round(gbs * 1e9 / (2 * mean_px), 0)
     return out
 
 
