@@ -149,6 +149,37 @@ def test_tile_shapes_ragged(px, rows, lanes):
         assert (g2 == gn).all()
 
 
+@pytest.mark.parametrize("kind", ["depth_f32", "depth_u16", "depth_f16", "disparity_f32"])
+def test_every_variant(kind):
+    """Every input kind x gradient filter x aggregation x output type, on a
+    67x132 frame (ragged in both directions) with the heuristic tile and with
+    4-column half-wave tiles of 5 rows: all 128 kernel instantiations of the
+    kind against the oracle."""
+    H, W = 67, 132
+    tc = 1.0
+    if kind == "disparity_f32":
+        f = 721.5 * W / 1242
+        cam = S.Camera(H, W, f, f, (W - 1) / 2, (H - 1) / 2)
+        raw = S.make_road(2300, cam).raw.numpy()
+        tc = S.ROAD_BASELINE
+    elif kind == "depth_u16":
+        cam = S.camera_for(H, W)
+        raw = S.make_u16(2301, cam).raw.numpy()
+    else:
+        cam = S.camera_for(H, W)
+        raw = S.make_cluttered(2302, cam).raw.numpy()
+        if kind == "depth_f16":
+            raw = raw.astype(np.float16)
+    half = sne.Context(0)
+    half.set_tile(4, 5, 32)
+    for ctx, tname in [(None, "auto"), (half, "4x5 half-wave")]:
+        for grad in GRADS:
+            for agg in AGGS:
+                for out in ("f32", "f16"):
+                    run_case(raw, kind, cam.as_tuple(), grad, agg, out, ctx=ctx, tc=tc,
+                             label="%s %s-%s %s %s" % (kind, grad, agg, out, tname))
+
+
 # ---------------------------------------------------------------- edge cases
 
 @pytest.mark.parametrize("shape", [(1, 1), (2, 5), (3, 3), (3, 130), (130, 3), (4, 1000),
