@@ -17,6 +17,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -33,7 +34,13 @@ def log(*a):
 
 
 def kernel_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    """Hash of the kernel source without comments and blank space, so that a
+    change of wording does not orphan the recorded counters."""
+    src = open(KERNEL_SRC).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    src = re.sub(r"\s+", " ", src)
+    return hashlib.sha256(src.encode()).hexdigest()[:16]
 
 
 def measured_traffic(workload: str, tile):

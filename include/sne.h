@@ -95,13 +95,16 @@ typedef struct sne_ctx sne_ctx;
  * cache of the autotuner.  *out is set to NULL on failure. */
 int sne_ctx_create(sne_ctx **out, int device);
 
-/* Wait for work the context enqueued, then free it.  NULL is accepted. */
+/* Wait for work the context enqueued, then free it.  NULL is accepted.
+ * SNE_ERR_STATE while a server created on ctx still exists. */
 int sne_ctx_destroy(sne_ctx *ctx);
 
 /* One frame: `in` is [H][in_pitch] of the kind's element type; normals
  * [3][H][out_pitch] of the out type; mask [H][mask_pitch] uint8 or NULL.
  * H, W >= 1 (frames smaller than 3x3 have no interior: all masked).  ctx may
- * be NULL (default tile shape).  One kernel launch. */
+ * be NULL (default tile shape).  One kernel launch.  The kernels address a
+ * frame with 32-bit byte offsets: SNE_ERR_UNSUPPORTED when (H + 2) rows of
+ * input pitch reach 2^31 bytes or a normal plane or the mask reaches 4 GiB. */
 int sne_estimate(sne_ctx *ctx, const void *in, int32_t H, int32_t W, int64_t in_pitch,
                  const sne_intrinsics *K, int kind, int grad, int agg, int out_type,
                  void *normals, int64_t out_pitch, uint8_t *mask, int64_t mask_pitch,
@@ -130,7 +133,9 @@ typedef struct {
 } sne_frame;
 
 /* Copy n intrinsics records (host memory) into the context's device-resident
- * table, replacing it; frames of sne_estimate_batched refer to its rows. */
+ * table, replacing it; frames of sne_estimate_batched refer to its rows.
+ * Waits for the context's own batches; SNE_ERR_STATE while a server created
+ * on ctx exists (its batches read the table when they run). */
 int sne_set_intrinsics_table(sne_ctx *ctx, const sne_intrinsics *K, int32_t n);
 
 /* n frames of any sizes (host array of descriptors) in ONE persistent launch:

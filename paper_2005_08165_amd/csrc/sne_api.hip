@@ -246,7 +246,6 @@ int batched_impl(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int
     if (n == 0) return SNE_OK;
     // validate every descriptor before touching the GPU
     int pxmax = 4;
-    int64_t total_px = 0;
     int maxH = 0, maxW = 0;
     for (int32_t i = 0; i < n; ++i) {
         const sne_frame &f = frames[i];
@@ -259,7 +258,6 @@ int batched_impl(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int
         pxmax = std::min(pxmax, max_px(f.in, f.normals, f.mask, f.W, f.in_pitch, f.out_pitch,
                                        f.mask_pitch, 0, 0, 0, (int64_t)f.H * f.out_pitch, kind,
                                        out_type));
-        total_px += (int64_t)f.H * f.W;
         maxH = std::max(maxH, (int)f.H);
         maxW = std::max(maxW, (int)f.W);
     }
@@ -321,7 +319,6 @@ int batched_impl(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int
     if (e != hipSuccess) return SNE_ERR_HIP;
     if (hipEventRecord(s.done, st) != hipSuccess) return SNE_ERR_HIP;
     s.used = true;
-    (void)total_px;
     return SNE_OK;
 }
 
@@ -386,6 +383,7 @@ int sne_ctx_create(sne_ctx **out, int device) {
 
 int sne_ctx_destroy(sne_ctx *ctx) {
     if (!ctx) return SNE_OK;
+    if (ctx->n_servers.load() > 0) return SNE_ERR_STATE;
     hipSetDevice(ctx->device);
     for (auto &s : ctx->slots) {
         if (s.used && s.done) hipEventSynchronize(s.done);
@@ -420,6 +418,7 @@ int sne_set_intrinsics_table(sne_ctx *ctx, const sne_intrinsics *K, int32_t n) {
     if (!ctx || !K || n < 1) return SNE_ERR_ARG;
     for (int32_t i = 0; i < n; ++i)
         if (!valid_K(&K[i], SNE_DEPTH_F32)) return SNE_ERR_ARG;
+    if (ctx->n_servers.load() > 0) return SNE_ERR_STATE;
     hipSetDevice(ctx->device);
     // wait for batches that may still read the old table
     for (auto &s : ctx->slots)

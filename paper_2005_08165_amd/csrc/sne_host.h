@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <map>
 #include <string>
 #include <tuple>
@@ -79,13 +80,16 @@ struct sne_ctx {
     int device = 0;
     int num_cu = 256;
     std::string arch;
-    sne::TileChoice forced{0, 0, 0};
+    sne::TileChoice forced{0, 0, 0, 0};
     std::map<sne::TileKey, sne::TileChoice> cache;
     sne_intrinsics *d_K = nullptr;
     int32_t nK = 0;
     sne::Slot slots[sne::kSlots];
     int next_slot = 0;
     int occ_blocks = 0;  // resident workgroups per CU for the persistent grid
+    // servers created on this context: their scheduler threads read d_K, so
+    // the table may not be replaced (nor the context destroyed) meanwhile
+    std::atomic<int> n_servers{0};
 };
 
 namespace sne {

@@ -4,11 +4,13 @@
 // instantiations build in parallel.
 //
 // Work decomposition.  A tile is `64 * PX` columns by `rows` rows of one
-// frame and belongs to one 64-lane wavefront; lane l owns columns
-// c0 + l*PX .. c0 + l*PX + PX-1 and walks down the rows of the tile keeping a
-// three-row window in registers.  Horizontal neighbours that live in the
-// adjacent lane arrive by DPP wave shifts; the two columns just outside the
-// tile are loaded by lanes 0 and 63 and enter through the DPP "old" operand.
+// frame and belongs to one 64-lane wavefront (or, in half-wave mode, two
+// tiles of `32 * PX` columns, one above the other, belong to the two halves of
+// a wavefront); lane l owns columns c0 + l*PX .. c0 + l*PX + PX-1 and walks
+// down the rows of its tile keeping a three-row window in registers.
+// Horizontal neighbours that live in the adjacent lane arrive by DPP wave
+// shifts; the two columns just outside a tile are loaded by its first and
+// last lanes and enter through the DPP "old" operand.
 // No LDS and no barriers are involved, so a tile's arithmetic is the same
 // instruction sequence whatever the launch shape: results are bitwise
 // identical alone, in a uniform batch and in an uneven persistent batch.
@@ -41,7 +43,6 @@
 #error "compile with -DSNE_KIND=<0..3>"
 #endif
 
-// Rows loaded ahead of the row being finished (1 or 2).
 // Minimum wavefronts per SIMD the register allocator has to leave room for
 // (0: the compiler's choice).
 #ifndef SNE_WAVES_PER_EU
@@ -65,6 +66,7 @@
 #define SNE_BATCH_OCCUPANCY
 #endif
 
+// Rows whose loads are in flight while a row is computed (1 or 2).
 #ifndef SNE_PREFETCH_ROWS
 #define SNE_PREFETCH_ROWS 1
 #endif
@@ -94,9 +96,10 @@ __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x);
 
 // Min/max of values the compiler cannot prove canonical (they come from
 // other basic blocks or earlier loop iterations) would each be preceded by a
-// quieting v_max x, x, x in IEEE mode.  Every operand below is a finite
-// product or reciprocal or an infinity, never a NaN, so the instructions are
-// issued directly.
+// quieting v_max x, x, x in IEEE mode.  For every pixel whose result is kept
+// the operands are finite or infinite, never NaN (a NaN can only arise in a
+// window with an invalid sample, whose output is replaced by zeros), so the
+// instructions are issued directly.
 __device__ __forceinline__ float vmin(float a, float b) {
     float r;
     asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
@@ -159,7 +162,8 @@ template <typename T, int N> struct alignas(sizeof(T) * N) Vec { T v[N]; };
 
 template <int KIND, int PX> struct RawRow {
     Vec<typename Raw<KIND>::T, PX> x;
-    typename Raw<KIND>::T h;  // halo sample: lane 0 left, lane 63 right
+    typename Raw<KIND>::T h;  // halo: a tile's first lane loads the column left
+                              // of it, its last lane the column right of it
 };
 
 // A frame's input as a buffer resource: loads outside [0, bytes) return 0

@@ -2,6 +2,7 @@
 #include "sne_sched.h"
 
 #include <algorithm>
+#include <cmath>
 
 namespace sne {
 namespace sched {
@@ -43,6 +44,42 @@ void Arena::release(uint64_t offset, uint64_t bytes) {
     }
     holes_[off] = len;
     free_ += bytes;
+}
+
+namespace {
+constexpr double kHistLo = 1e-7;     // seconds: lower edge of bin 0
+constexpr double kHistRatio = 1.01;  // upper / lower edge of a bin
+constexpr int kHistBins = 2546;      // up to 1e-7 * 1.01^2546 > 1e4 s
+}  // namespace
+
+LatencyHistogram::LatencyHistogram() : bins_(kHistBins, 0) {}
+
+void LatencyHistogram::add(double s) {
+    if (!(s >= 0.0)) s = 0.0;
+    int b = s <= kHistLo ? 0 : (int)(std::log(s / kHistLo) / std::log(kHistRatio));
+    b = std::min(std::max(b, 0), kHistBins - 1);
+    ++bins_[b];
+    if (n_ == 0 || s < min_) min_ = s;
+    if (n_ == 0 || s > max_) max_ = s;
+    ++n_;
+}
+
+double LatencyHistogram::quantile(double q) const {
+    if (n_ == 0) return 0.0;
+    // the same rank rule as quantile(vector): index floor(q n), at most n - 1
+    uint64_t k = (uint64_t)(q * (double)n_);
+    if (k >= n_) k = n_ - 1;
+    if (k == 0) return min_;
+    if (k == n_ - 1) return max_;
+    uint64_t seen = 0;
+    for (int b = 0; b < kHistBins; ++b) {
+        seen += bins_[b];
+        if (seen > k) {
+            const double hi = kHistLo * std::pow(kHistRatio, b + 1);
+            return std::min(std::max(hi, min_), max_);
+        }
+    }
+    return max_;
 }
 
 Scheduler::Scheduler(const Config &cfg, Executor *ex)
@@ -90,7 +127,7 @@ void Scheduler::retire(double now) {
             if (rc == 0) {
                 ++stats_.completed;
                 stats_.pixels_done += (uint64_t)q->H * q->W;
-                stats_.latencies.push_back(q->t_done - q->t_arrival);
+                stats_.latency.add(q->t_done - q->t_arrival);
             } else {
                 ++stats_.failed;
             }

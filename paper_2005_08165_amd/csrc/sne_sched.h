@@ -37,7 +37,8 @@ struct Request {
     bool has_output = false;  // out_offset holds an arena allocation
     bool finished = false;    // completed or failed
     int status = 0;
-    const void *payload = nullptr;  // executor-specific (frame pointers, K row)
+    const void *in = nullptr;  // the frame (read by the executor only)
+    int64_t in_pitch = 0;      // its row pitch in elements
 };
 
 struct Config {
@@ -81,11 +82,29 @@ struct Executor {
     virtual int result(const Batch &b) { (void)b; return 0; }
 };
 
+// Latency distribution in fixed memory: logarithmic bins 1 % wide from
+// 0.1 us to 10^4 s, so a server can run indefinitely.  Quantiles are exact to
+// the bin (within 1 %), clamped to the exact minimum and maximum.
+class LatencyHistogram {
+public:
+    LatencyHistogram();
+    void add(double seconds);
+    uint64_t count() const { return n_; }
+    double max() const { return n_ ? max_ : 0.0; }
+    // nearest-rank quantile, q in [0, 1]; 0 if empty
+    double quantile(double q) const;
+
+private:
+    std::vector<uint64_t> bins_;
+    uint64_t n_ = 0;
+    double min_ = 0.0, max_ = 0.0;
+};
+
 struct Stats {
     uint64_t submitted = 0, rejected_full = 0, rejected_budget = 0, completed = 0, failed = 0;
     uint64_t batches = 0, frames_in_batches = 0, pixels_done = 0;
     double first_arrival = 0.0, last_done = 0.0;
-    std::vector<double> latencies;  // t_done - t_arrival of completed requests
+    LatencyHistogram latency;  // t_done - t_arrival of completed requests
 };
 
 class Scheduler {

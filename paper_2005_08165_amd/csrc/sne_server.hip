@@ -50,11 +50,6 @@ struct SlotRes {
 
 int px_index(int px) { return px == 4 ? 2 : (px == 2 ? 1 : 0); }
 
-struct Payload {
-    const void *in;
-    int64_t in_pitch;
-};
-
 class HipExecutor : public sched::Executor {
 public:
     sne_ctx *ctx = nullptr;
@@ -161,20 +156,18 @@ public:
         const size_t oe = out_elem(cfg.out_type);
         int px = 4;
         for (auto *q : b.reqs) {
-            const Payload *p = (const Payload *)q->payload;
             uint8_t *out = arena + q->out_offset;
             uint8_t *mask = out + 3 * (size_t)q->H * q->W * oe;
-            px = std::min(px, max_px(p->in, out, mask, q->W, p->in_pitch, q->W, q->W, 0, 0, 0,
+            px = std::min(px, max_px(q->in, out, mask, q->W, q->in_pitch, q->W, q->W, 0, 0, 0,
                                      (int64_t)q->H * q->W, cfg.kind, cfg.out_type));
         }
         int64_t tiles = 0;
         for (size_t i = 0; i < b.reqs.size(); ++i) {
             auto *q = b.reqs[i];
-            const Payload *p = (const Payload *)q->payload;
             uint8_t *out = arena + q->out_offset;
             uint8_t *mask = out + 3 * (size_t)q->H * q->W * oe;
             const sne_intrinsics unused{1.f, 1.f, 0.f, 0.f};  // the kernel reads the table
-            fd[i] = make_desc(p->in, out, mask, q->H, q->W, p->in_pitch, q->W, q->W, unused);
+            fd[i] = make_desc(q->in, out, mask, q->H, q->W, q->in_pitch, q->W, q->W, unused);
             fd[i].k_index = q->stream;
             const int nst = (q->W + 64 * px - 1) / (64 * px);
             const int nb = (q->H + rows - 1) / rows;
@@ -232,8 +225,6 @@ struct sne_server {
     std::thread worker;
     std::atomic<bool> stop{false};
     sne::Clock::time_point t0;
-    std::vector<sne::Payload *> payloads;  // freed at destroy (one per request)
-    std::mutex pay_mu;
 
     double now() const {
         return std::chrono::duration<double>(sne::Clock::now() - t0).count();
@@ -279,11 +270,11 @@ void fill_stats(const sched::Stats &st, uint64_t arena_free, sne_server_stats *o
     o->rejected_budget = st.rejected_budget;
     o->batches = st.batches;
     o->mean_batch_frames = st.batches ? (double)st.frames_in_batches / st.batches : 0.0;
-    o->latency_p50 = sched::quantile(st.latencies, 0.50);
-    o->latency_p90 = sched::quantile(st.latencies, 0.90);
-    o->latency_p99 = sched::quantile(st.latencies, 0.99);
-    o->latency_p999 = sched::quantile(st.latencies, 0.999);
-    o->latency_max = sched::quantile(st.latencies, 1.0);
+    o->latency_p50 = st.latency.quantile(0.50);
+    o->latency_p90 = st.latency.quantile(0.90);
+    o->latency_p99 = st.latency.quantile(0.99);
+    o->latency_p999 = st.latency.quantile(0.999);
+    o->latency_max = st.latency.max();
     const double span = st.last_done - st.first_arrival;
     if (span > 0) {
         o->mpix_per_s = (double)st.pixels_done / span / 1e6;
@@ -328,6 +319,7 @@ int sne_server_create(sne_server **out, sne_ctx *ctx, const sne_server_config *c
     sc.queue_capacity = (size_t)cfg->queue_capacity;
     s->sched = new sched::Scheduler(sc, &s->ex);
     s->t0 = Clock::now();
+    ctx->n_servers.fetch_add(1);
     s->worker = std::thread(worker_loop, s);
     *out = s;
     return SNE_OK;
@@ -342,24 +334,17 @@ int sne_server_submit(sne_server *srv, const sne_request *req, uint64_t *ticket)
     if (req->stream_id < 0 || req->stream_id >= srv->ctx->nK) return SNE_ERR_ARG;
     if (!frame_fits(req->H, req->in_pitch, srv->cfg.kind, req->W, srv->cfg.out_type, req->W))
         return SNE_ERR_UNSUPPORTED;
-    Payload *p = new Payload{req->in, req->in_pitch};
     sched::Request r;
     r.stream = req->stream_id;
     r.H = req->H;
     r.W = req->W;
     r.out_bytes = out_bytes(srv->cfg, req->H, req->W);
-    r.payload = p;
+    r.in = req->in;
+    r.in_pitch = req->in_pitch;
     std::lock_guard<std::mutex> lk(srv->mu);
     r.t_arrival = req->t_arrival >= 0 ? req->t_arrival : srv->now();
     const int rc = srv->sched->submit(r, ticket);
-    if (rc != 0) {
-        delete p;
-        return rc == -3 ? SNE_ERR_BUDGET : SNE_ERR_FULL;
-    }
-    {
-        std::lock_guard<std::mutex> pk(srv->pay_mu);
-        srv->payloads.push_back(p);
-    }
+    if (rc != 0) return rc == -3 ? SNE_ERR_BUDGET : SNE_ERR_FULL;
     return SNE_OK;
 }
 
@@ -431,7 +416,7 @@ int sne_server_destroy(sne_server *srv) {
     srv->ex.destroy();
     delete srv->sched;
     if (srv->arena) (void)hipFree(srv->arena);
-    for (auto *p : srv->payloads) delete p;
+    srv->ctx->n_servers.fetch_sub(1);
     delete srv;
     return SNE_OK;
 }

@@ -225,8 +225,10 @@ class Context:
         return self._h
 
     def close(self):
+        """Free the context (SneError with SNE_ERR_STATE while a Server on it
+        is still open; the context then stays usable)."""
         if self._h:
-            lib().sne_ctx_destroy(self._h)
+            check("sne_ctx_destroy", lib().sne_ctx_destroy(self._h))
             self._h = ctypes.c_void_p()
 
     def __del__(self):

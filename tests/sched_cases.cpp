@@ -265,7 +265,36 @@ static void case_quantile() {
     std::printf("ok quantile\n");
 }
 
+// The fixed-memory latency histogram agrees with exact nearest-rank
+// quantiles within its 1 % bins, keeps the exact maximum, and a long run adds
+// no memory (the latencies are not stored).
+static void case_latency_histogram() {
+    std::mt19937_64 g(7);
+    std::lognormal_distribution<double> d(std::log(400e-6), 0.8);
+    LatencyHistogram h;
+    std::vector<double> v;
+    for (int i = 0; i < 200000; ++i) {
+        const double x = d(g);
+        h.add(x);
+        v.push_back(x);
+    }
+    CHECK(h.count() == v.size());
+    for (double q : {0.0, 0.1, 0.5, 0.9, 0.99, 0.999, 1.0}) {
+        const double exact = quantile(v, q), got = h.quantile(q);
+        CHECK(got >= exact * (1 - 1e-12) && got <= exact * 1.0101);
+    }
+    CHECK(h.max() == quantile(v, 1.0));
+    LatencyHistogram e;
+    CHECK(e.quantile(0.5) == 0 && e.max() == 0);
+    e.add(0.0);
+    e.add(-1.0);                                // clock skew: counted as 0
+    e.add(1e9);                                 // beyond the last bin
+    CHECK(e.count() == 3 && e.max() == 1e9 && e.quantile(0.0) == 0.0);
+    std::printf("ok latency_histogram\n");
+}
+
 int main() {
+    case_latency_histogram();
     case_arena();
     case_continuous_batching();
     case_budget_admission_fifo();

@@ -431,7 +431,9 @@ def test_full_size_batch64_sobel_median():
     cam = S.Camera(480, 640, *S.INDOOR_K)
     say("generating 64 frames")
     raw = torch.stack([S.make_cluttered(1000 + i, cam, device="cuda").raw for i in range(64)])
-    n, m = sne.estimate_uniform(raw, cam.as_tuple(), "depth_f32", "sobel", "median")
+    ctx = sne.Context(0)   # with the shipped tuning table, as the benchmark
+    say("tile", ctx.get_tile(480, 640, 64, "depth_f32", "sobel", "median", "f32"))
+    n, m = sne.estimate_uniform(raw, cam.as_tuple(), "depth_f32", "sobel", "median", ctx=ctx)
     torch.cuda.synchronize()
     _sampled_parity(raw, n, m, cam.as_tuple(), "depth_f32", "sobel", "median", "f32", 8, 20000, 1)
 
@@ -440,7 +442,8 @@ def test_full_size_disparity_batch128():
     cam = S.ROAD_CAM
     say("generating 128 disparity frames")
     raw = torch.stack([S.make_road(2000 + i, device="cuda").raw for i in range(128)])
-    n, m = sne.estimate_uniform(raw, cam.as_tuple(), "disparity_f32", "scharr", "median")
+    n, m = sne.estimate_uniform(raw, cam.as_tuple(), "disparity_f32", "scharr", "median",
+                                ctx=sne.Context(0))
     torch.cuda.synchronize()
     _sampled_parity(raw, n, m, cam.as_tuple(), "disparity_f32", "scharr", "median", "f32", 6,
                     20000, 2, tc=S.ROAD_BASELINE)

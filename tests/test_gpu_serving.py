@@ -100,7 +100,16 @@ def test_budget_backpressure_and_errors():
     rest = srv.poll(8)
     assert len(rest) == 1 and rest[0].status == 0
     srv.release(rest[0].ticket)
+    # the intrinsics table and the context stay fixed while a server uses them
+    with pytest.raises(sne.SneError) as ei:
+        ctx.set_intrinsics_table([c.as_tuple() for c in cams])
+    assert ei.value.status == -5
+    with pytest.raises(sne.SneError) as ei:
+        ctx.close()
+    assert ei.value.status == -5
     srv.close()
+    ctx.set_intrinsics_table([c.as_tuple() for c in cams])
+    ctx.close()
 
 
 def test_open_loop_small():
