@@ -22,7 +22,7 @@
  *   3. Depth z of each window sample: the raw value for depth kinds; for a
  *      disparity image z = f t_c / d with f = fx = fy (eq. z_d).
  *   4. The filtered image s: inverse depth 1/z for depth kinds (the image
- *      "storing the values of 1/z" of Sec. III), the raw disparity d for the
+ *      the gradient filters of Sec. III run on), the raw disparity d for the
  *      disparity kind (eq. nx2_ny2_nz3).
  *   5. Filters 1 and 2: G_u = K_x (*) s and G_v = K_y (*) s over the 3x3
  *      window (correlation, so G_u approximates +ds/du), K_y = K_x^T, with the
