@@ -174,15 +174,18 @@ def serving(torch, S, sne, duration=2.0, slo_p99_ms=2.0,
     mean_px = float(np.mean([h * w for h, w in shapes]))
     out = {"streams": 64, "mean_mpix_per_frame": round(mean_px / 1e6, 3),
            "slo_p99_ms": slo_p99_ms, "runs": []}
-    for agg, rates in plan:
+    # the last entry of the plan replays no graphs: the same batches as plain launches
+    plan = tuple((agg, rates, True) for agg, rates in plan) + (("mean", (60000,), False),)
+    for agg, rates, graphs in plan:
         srv = sne.Server(ctx, "depth_u16", "fd", agg, "f16", max_inflight=3,
-                         max_batch_frames=256, hbm_budget_bytes=16 << 30, use_graphs=True)
+                         max_batch_frames=256, hbm_budget_bytes=16 << 30, use_graphs=graphs)
         for lam in rates:
-            log("serving FD-%s at %d frames/s" % (agg, lam))
+            log("serving FD-%s at %d frames/s%s" % (agg, lam, "" if graphs else ", no graphs"))
             st = srv.run_open_loop(rings, total_rate=lam, duration_s=duration, seed=5000,
                                    n_producers=8)
             p99 = st["latency_p99"] * 1e3
-            out["runs"].append({"agg": agg, "offered_fps": lam, "completed": st["completed"],
+            out["runs"].append({"agg": agg, "graphs": graphs, "offered_fps": lam,
+                                "completed": st["completed"],
                                 "p50_ms": round(st["latency_p50"] * 1e3, 3),
                                 "p99_ms": round(p99, 3),
                                 "p999_ms": round(st["latency_p999"] * 1e3, 3),
