@@ -134,3 +134,17 @@ def test_frames_past_the_32bit_offset_limits_are_rejected():
     assert est(2 * 16387 + 1, W, W, 1, 1, W, W) == -2  # u16 input: twice the rows + 1
     assert est(1024, 1000, 1000, 0, 0, 1 << 20, 1000) == -2   # output plane = 4 GiB
     assert est(1024, 1000, 1000, 0, 0, 1000, 1 << 22) == -2   # mask = 4 GiB
+
+
+def test_c_client_builds(tmp_path):
+    """The C ABI client compiles against include/sne.h and links libsne and
+    the oracle with a plain C++ compiler (it runs in the GPU tests)."""
+    import shutil
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import c_client_build
+    if shutil.which("g++") is None:
+        pytest.skip("no g++")
+    import oracle
+    oracle.build(force=False)
+    assert os.path.exists(c_client_build.build())
