@@ -87,18 +87,22 @@ def plain_single_frame(torch, S, sne, grad, agg, reps=200):
     K = fr.cam.as_tuple()
     nrm = torch.empty((3, 480, 640), device="cuda")
     msk = torch.empty((480, 640), dtype=torch.uint8, device="cuda")
+    ctx = sne.Context(0)
+
+    def one(i=0):
+        sne.estimate(raw, K, "depth_f32", grad, agg, normals=nrm, mask=msk, ctx=ctx)
+
     for _ in range(20):
-        sne.estimate(raw, K, "depth_f32", grad, agg, normals=nrm, mask=msk)
+        one()
     torch.cuda.synchronize()
     lat = []
     for _ in range(reps):
         t0 = time.perf_counter()
-        sne.estimate(raw, K, "depth_f32", grad, agg, normals=nrm, mask=msk)
+        one()
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - t0)
     lat.sort()
-    wall, ev = time_launches(torch, lambda i: sne.estimate(raw, K, "depth_f32", grad, agg,
-                                                           normals=nrm, mask=msk), 20, reps)
+    wall, ev = time_launches(torch, one, 20, reps)
     px = 480 * 640
     return {"variant": "%s-%s" % (grad, agg), "mpix_per_s": round(px * reps / ev / 1e6, 1),
             "frames_per_s": round(reps / ev, 1),
