@@ -114,7 +114,8 @@ int sne_estimate(sne_ctx *ctx, const void *in, int32_t H, int32_t W, int64_t in_
  * in + b * in_frame_stride and writes normals + b * out_frame_stride and
  * mask + b * mask_frame_stride (strides in elements; an output frame stride
  * must be at least 3 * H * out_pitch).  Bitwise identical, frame by frame, to
- * B calls of sne_estimate. */
+ * B calls of sne_estimate.  B = 0 launches nothing (the pointers may then be
+ * NULL). */
 int sne_estimate_uniform(sne_ctx *ctx, const void *in, int32_t B, int32_t H, int32_t W,
                          int64_t in_pitch, int64_t in_frame_stride, const sne_intrinsics *K,
                          int kind, int grad, int agg, int out_type, void *normals,
@@ -142,6 +143,7 @@ int sne_set_intrinsics_table(sne_ctx *ctx, const sne_intrinsics *K, int32_t n);
  * a grid sized to the GPU pulls tiles from a device counter until every tile
  * of every frame is done.  All frames share kind, grad, agg and out type.
  * Bitwise identical, frame by frame, to sne_estimate with the same K.
+ * n = 0 launches nothing (frames may then be NULL).
  * The descriptor table is staged through pinned memory owned by the context,
  * so the host array may be reused as soon as the call returns; a further call
  * on the same context waits for the previous batch's staging copy. */

@@ -158,15 +158,15 @@ int uniform_impl(sne_ctx *ctx, const void *in, int32_t B, int32_t H, int32_t W, 
                  int64_t in_fs, const sne_intrinsics *K, int kind, int grad, int agg, int out_type,
                  void *normals, int64_t out_pitch, int64_t out_fs, uint8_t *mask,
                  int64_t mask_pitch, int64_t mask_fs, void *stream, const TileChoice *force) {
-    if (!in || !normals || !valid_enum(kind, grad, agg, out_type) || !valid_K(K, kind))
-        return SNE_ERR_ARG;
+    if (!valid_enum(kind, grad, agg, out_type) || !valid_K(K, kind)) return SNE_ERR_ARG;
     if (B < 0 || H < 1 || W < 1 || in_pitch < W || out_pitch < W) return SNE_ERR_ARG;
     if (mask && mask_pitch < W) return SNE_ERR_ARG;
+    if (B == 0) return SNE_OK;  // an empty batch: the pointers may be NULL
+    if (!in || !normals) return SNE_ERR_ARG;
     const int64_t plane = (int64_t)H * out_pitch;
     if (B > 1 && (in_fs < (int64_t)H * in_pitch || out_fs < 3 * plane ||
                   (mask && mask_fs < (int64_t)H * mask_pitch)))
         return SNE_ERR_ARG;
-    if (B == 0) return SNE_OK;
     if (B == 1) {
         in_fs = 0;
         out_fs = 0;
@@ -242,8 +242,9 @@ int ensure_slot(Slot &s, size_t n) {
 
 int batched_impl(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int grad, int agg,
                  int out_type, void *stream, const TileChoice *force) {
-    if (!ctx || !frames || n < 0 || !valid_enum(kind, grad, agg, out_type)) return SNE_ERR_ARG;
-    if (n == 0) return SNE_OK;
+    if (!ctx || n < 0 || !valid_enum(kind, grad, agg, out_type)) return SNE_ERR_ARG;
+    if (n == 0) return SNE_OK;  // an empty batch: frames may be NULL
+    if (!frames) return SNE_ERR_ARG;
     // validate every descriptor before touching the GPU
     int pxmax = 4;
     int maxH = 0, maxW = 0;

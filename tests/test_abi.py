@@ -59,9 +59,14 @@ def test_uniform_argument_errors():
                                   FAKE, 10, 299, FAKE, 10, 100, None) == -1
     assert L.sne_estimate_uniform(None, FAKE, -1, 10, 10, 10, 100, ctypes.byref(K), 0, 0, 0, 0,
                                   FAKE, 10, 300, FAKE, 10, 100, None) == -1
-    # B = 0 is a valid empty batch: nothing is launched
+    # B = 0 is a valid empty batch: nothing is launched, NULL pointers allowed
     assert L.sne_estimate_uniform(None, FAKE, 0, 10, 10, 10, 100, ctypes.byref(K), 0, 0, 0, 0,
                                   FAKE, 10, 300, FAKE, 10, 100, None) == 0
+    assert L.sne_estimate_uniform(None, None, 0, 10, 10, 10, 0, ctypes.byref(K), 0, 0, 0, 0,
+                                  None, 10, 0, None, 10, 0, None) == 0
+    # ... but not NULL pointers for a real frame
+    assert L.sne_estimate_uniform(None, None, 1, 10, 10, 10, 0, ctypes.byref(K), 0, 0, 0, 0,
+                                  FAKE, 10, 0, None, 10, 0, None) == -1
 
 
 def test_null_context_errors():

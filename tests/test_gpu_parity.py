@@ -214,6 +214,23 @@ def test_all_invalid_and_constant_frames():
             run_case(raw, "depth_f32", (50.0, 50.0, 35.0, 20.0), "sobel", agg, label="flat")
 
 
+def test_empty_batches():
+    """A uniform batch of 0 frames and an uneven batch of 0 frames launch
+    nothing and succeed; a batch of one frame equals the single call."""
+    ctx = sne.Context(0)
+    raw = torch.zeros((0, 24, 40), device="cuda")
+    n, m = sne.estimate_uniform(raw, (30.0, 30.0, 19.5, 11.5), "depth_f32", "fd", "mean", ctx=ctx)
+    assert n.shape == (0, 3, 24, 40) and m.shape == (0, 24, 40)
+    ctx.set_intrinsics_table([(30.0, 30.0, 19.5, 11.5)])
+    normals, masks = ctx.estimate_batched([], [], "depth_f32", "fd", "mean", "f32")
+    assert normals == [] and masks == []
+    one = torch.rand((24, 40), device="cuda") + 1.0
+    nb, mb = ctx.estimate_batched([one], [0], "depth_f32", "fd", "mean", "f32")
+    n1, m1 = sne.estimate(one, (30.0, 30.0, 19.5, 11.5), "depth_f32", "fd", "mean", ctx=ctx)
+    torch.cuda.synchronize()
+    assert torch.equal(nb[0], n1) and torch.equal(mb[0], m1)
+
+
 KW = {"fd": (0, 1, 0), "sobel": (1, 2, 1), "scharr": (3, 10, 3), "prewitt": (1, 1, 1)}
 
 
