@@ -155,7 +155,7 @@ def uneven_batch(torch, S, sne, agg, n_frames=1024, reps=5, autotune=False):
             "note": "event time per call: descriptor staging copy + counter reset + kernel"}
 
 
-def serving(torch, S, sne, duration=2.0, slo_p99_ms=2.0,
+def serving(torch, S, sne, duration=2.0, slo_p99_ms=2.0, plain_run=True,
             plan=(("mean", (20000, 60000, 100000, 120000, 140000, 160000)),
                   ("median", (20000, 60000, 100000, 120000, 140000)))):
     """64 sensor streams (resolution per stream drawn with seed 5001 from
@@ -178,8 +178,10 @@ def serving(torch, S, sne, duration=2.0, slo_p99_ms=2.0,
     mean_px = float(np.mean([h * w for h, w in shapes]))
     out = {"streams": 64, "mean_mpix_per_frame": round(mean_px / 1e6, 3),
            "slo_p99_ms": slo_p99_ms, "runs": []}
-    # the last entry of the plan replays no graphs: the same batches as plain launches
-    plan = tuple((agg, rates, True) for agg, rates in plan) + (("mean", (60000,), False),)
+    # an extra run replays no graphs: the same batches as plain launches
+    plan = tuple((agg, rates, True) for agg, rates in plan)
+    if plain_run:
+        plan += (("mean", (60000,), False),)
     for agg, rates, graphs in plan:
         srv = sne.Server(ctx, "depth_u16", "fd", agg, "f16", max_inflight=3,
                          max_batch_frames=256, hbm_budget_bytes=16 << 30, use_graphs=graphs)
@@ -260,6 +262,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-rate", type=float, default=0.0,
+                    help="run the serving loop at this one offered rate (FD-mean) only")
     ap.add_argument("--autotune", action="store_true",
                     help="tune the tile shape live instead of using the shipped table")
     ap.add_argument("--tile", default="",
@@ -349,7 +353,11 @@ def main():
                                uneven_batch(torch, S, sne, "median")]
     if not args.no_serving:
         log("serving loop")
-        res["serving"] = serving(torch, S, sne)
+        if args.serving_rate > 0:
+            res["serving"] = serving(torch, S, sne, plain_run=False,
+                                     plan=(("mean", (args.serving_rate,)),))
+        else:
+            res["serving"] = serving(torch, S, sne)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         host = bufs[0][0].cpu().numpy()
