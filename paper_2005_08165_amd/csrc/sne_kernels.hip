@@ -656,13 +656,29 @@ __global__ __launch_bounds__(kBlock) SNE_OCCUPANCY void sne_uniform_kernel(Unifo
                                            a.wa, a.wb);
 }
 
+// A value loaded through a generic pointer counts as lane-varying for the
+// compiler, even at a wave-uniform address.  The batch tables are only read
+// at wave-uniform addresses: moving every dword to a scalar register keeps
+// the frame's buffer resource and constants in SGPRs (otherwise each buffer
+// load of the tile becomes a loop over distinct resources).
+template <typename T> __device__ __forceinline__ T uniform_load(const T *p) {
+    static_assert(sizeof(T) % 4 == 0, "dword-sized table entries");
+    struct Words {
+        int w[sizeof(T) / 4];
+    };
+    Words v = __builtin_bit_cast(Words, *p);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) v.w[i] = __builtin_amdgcn_readfirstlane(v.w[i]);
+    return __builtin_bit_cast(T, v);
+}
+
 // Persistent uneven batch: every wavefront pulls `chunk` consecutive tiles at
 // a time from a device counter until the queue is drained.
 template <int KIND, bool FD, int AGG, int OUT, int PX, bool HALF>
 __global__ __launch_bounds__(kBlock) SNE_BATCH_OCCUPANCY void sne_batch_kernel(BatchArgs a) {
     const int lane = threadIdx.x & (kWave - 1);
-    const int nframes = a.counts ? a.counts[0] : a.nframes;
-    const int ntiles = a.counts ? a.counts[1] : a.ntiles;
+    const int nframes = a.counts ? uniform_load(a.counts) : a.nframes;
+    const int ntiles = a.counts ? uniform_load(a.counts + 1) : a.ntiles;
     for (;;) {
         int base = 0;
         if (lane == 0) base = atomicAdd(a.counter, a.chunk);
@@ -674,17 +690,17 @@ __global__ __launch_bounds__(kBlock) SNE_BATCH_OCCUPANCY void sne_batch_kernel(B
             int lo = 0, hi = nframes - 1;
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
-                if (a.tile_start[mid] <= tile) lo = mid; else hi = mid - 1;
+                if (uniform_load(a.tile_start + mid) <= tile) lo = mid; else hi = mid - 1;
             }
             const int frame = lo;
-            FrameDesc f = a.frames[frame];
-            const float4 K = a.ktable[f.k_index];
+            FrameDesc f = uniform_load(a.frames + frame);
+            const float4 K = uniform_load(a.ktable + f.k_index);
             f.fx = K.x;
             f.fy = K.y;
             f.u0 = K.z;
             f.v0 = K.w;
-            const int local = tile - a.tile_start[frame];
-            const int ns = a.nstrips[frame];
+            const int local = tile - uniform_load(a.tile_start + frame);
+            const int ns = uniform_load(a.nstrips + frame);
             const int band = local / ns;
             const int strip = local - band * ns;
             const int r0 = band * a.rows * (HALF ? 2 : 1);
