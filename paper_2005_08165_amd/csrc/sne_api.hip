@@ -124,13 +124,6 @@ hipError_t launch_batch(const Variant &v, const BatchArgs &a, int grid, hipStrea
     }
 }
 
-__global__ void zero_counter(int32_t *c) { *c = 0; }
-
-hipError_t launch_zero_counter(int32_t *counter, hipStream_t s) {
-    hipLaunchKernelGGL(zero_counter, dim3(1), dim3(1), 0, s, counter);
-    return hipGetLastError();
-}
-
 FrameDesc make_desc(const void *in, void *out, uint8_t *mask, int H, int W, int64_t in_pitch,
                     int64_t out_pitch, int64_t mask_pitch, const sne_intrinsics &K) {
     FrameDesc f;
@@ -202,16 +195,9 @@ int uniform_impl(sne_ctx *ctx, const void *in, int32_t B, int32_t H, int32_t W, 
 }
 
 void free_slot(Slot &s) {
-    if (s.d_frames) hipFree(s.d_frames);
-    if (s.d_start) hipFree(s.d_start);
-    if (s.d_nstrips) hipFree(s.d_nstrips);
-    if (s.d_counter) hipFree(s.d_counter);
+    if (s.d_table) hipFree(s.d_table);
     if (s.h_stage) hipHostFree(s.h_stage);
     s = Slot{};
-}
-
-size_t stage_bytes(size_t cap) {
-    return cap * sizeof(FrameDesc) + (cap + 1) * sizeof(int32_t) + cap * sizeof(int32_t) + 64;
 }
 
 int ensure_slot(Slot &s, size_t n) {
@@ -225,11 +211,9 @@ int ensure_slot(Slot &s, size_t n) {
     s.done = ev;
     size_t cap = 64;
     while (cap < n) cap *= 2;
-    if (hipMalloc(&s.d_frames, cap * sizeof(FrameDesc)) != hipSuccess ||
-        hipMalloc(&s.d_start, (cap + 1) * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc(&s.d_nstrips, cap * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc(&s.d_counter, sizeof(int32_t)) != hipSuccess ||
-        hipHostMalloc(&s.h_stage, stage_bytes(cap), hipHostMallocDefault) != hipSuccess) {
+    if (hipMalloc(&s.d_table, batch_table_bytes((int64_t)cap)) != hipSuccess ||
+        hipHostMalloc(&s.h_stage, batch_table_bytes((int64_t)cap), hipHostMallocDefault) !=
+            hipSuccess) {
         ev = s.done;
         s.done = nullptr;
         free_slot(s);
@@ -273,42 +257,33 @@ int batched_impl(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int
     if (rc != SNE_OK) return rc;
     if (s.used && hipEventSynchronize(s.done) != hipSuccess) return SNE_ERR_HIP;
 
-    FrameDesc *hf = (FrameDesc *)s.h_stage;
-    int32_t *hstart = (int32_t *)(hf + s.cap);
-    int32_t *hns = hstart + s.cap + 1;
+    const BatchTable bt = batch_table(s.h_stage, n);
     int64_t tiles = 0;
     for (int32_t i = 0; i < n; ++i) {
         const sne_frame &f = frames[i];
         const sne_intrinsics unused{1.f, 1.f, 0.f, 0.f};  // the kernel reads the table
-        hf[i] = make_desc(f.in, f.normals, f.mask, f.H, f.W, f.in_pitch, f.out_pitch,
-                          f.mask_pitch, unused);
-        hf[i].k_index = f.k_index;
+        bt.frames[i] = make_desc(f.in, f.normals, f.mask, f.H, f.W, f.in_pitch, f.out_pitch,
+                                 f.mask_pitch, unused);
+        bt.frames[i].k_index = f.k_index;
         const int ns = tile_nstrips(f.W, t);
         const int nb = tile_nbands(f.H, t);
-        hstart[i] = (int32_t)tiles;
-        hns[i] = ns;
+        bt.tile_start[i] = (int32_t)tiles;
+        bt.nstrips[i] = ns;
         tiles += (int64_t)ns * nb;
         if (tiles > INT32_MAX / 2) return SNE_ERR_BUDGET;
     }
-    hstart[n] = (int32_t)tiles;
+    bt.tile_start[n] = (int32_t)tiles;
+    *bt.head = BatchHeader{};
+    bt.head->nframes = n;
+    bt.head->ntiles = (int32_t)tiles;
     hipStream_t st = (hipStream_t)stream;
-    if (hipMemcpyAsync(s.d_frames, hf, n * sizeof(FrameDesc), hipMemcpyHostToDevice, st) !=
-            hipSuccess ||
-        hipMemcpyAsync(s.d_start, hstart, (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st) !=
-            hipSuccess ||
-        hipMemcpyAsync(s.d_nstrips, hns, n * sizeof(int32_t), hipMemcpyHostToDevice, st) !=
-            hipSuccess)
+    // one copy of the used part of the table; it also zeroes the tile counter
+    if (hipMemcpyAsync(s.d_table, s.h_stage, batch_table_bytes(n), hipMemcpyHostToDevice, st) !=
+        hipSuccess)
         return SNE_ERR_HIP;
-    if (launch_zero_counter(s.d_counter, st) != hipSuccess) return SNE_ERR_HIP;
     BatchArgs a;
-    a.frames = s.d_frames;
-    a.tile_start = s.d_start;
-    a.nstrips = s.d_nstrips;
+    a.table = s.d_table;
     a.ktable = reinterpret_cast<const float4 *>(ctx->d_K);
-    a.counter = s.d_counter;
-    a.counts = nullptr;
-    a.nframes = n;
-    a.ntiles = (int32_t)tiles;
     a.rows = t.rows;
     a.chunk = 1;
     grad_weights(grad, a.wa, a.wb);

@@ -38,13 +38,10 @@ inline int tile_nbands(int H, const TileChoice &t) {
 }
 inline int kernel_px(const TileChoice &t) { return t.px + (t.half ? 100 : 0); }
 
-// Device tables of one in-flight uneven batch.
+// Tables of one in-flight uneven batch (layout: BatchTable).
 struct Slot {
-    FrameDesc *d_frames = nullptr;
-    int32_t *d_start = nullptr;
-    int32_t *d_nstrips = nullptr;
-    int32_t *d_counter = nullptr;
-    void *h_stage = nullptr;  // pinned: frames | start | nstrips
+    void *d_table = nullptr;
+    void *h_stage = nullptr;  // pinned staging of the same layout
     size_t cap = 0;           // frames capacity
     hipEvent_t done = nullptr;
     bool used = false;
@@ -72,7 +69,6 @@ int max_px(const void *in, const void *out, const uint8_t *mask, int W, int64_t 
 FrameDesc make_desc(const void *in, void *out, uint8_t *mask, int H, int W, int64_t in_pitch,
                     int64_t out_pitch, int64_t mask_pitch, const sne_intrinsics &K);
 hipError_t launch_batch(const Variant &v, const BatchArgs &a, int grid, hipStream_t s);
-hipError_t launch_zero_counter(int32_t *counter, hipStream_t s);
 
 }  // namespace sne
 

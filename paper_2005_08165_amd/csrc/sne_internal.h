@@ -35,16 +35,48 @@ struct UniformArgs {
     float wa, wb;                   // 3-row filters: wa = side / centre weight; wb unused (1)
 };
 
-// Uneven batch, persistent grid pulling tiles from a device counter.
+// Uneven batch.  Its tables are one block of device memory that the host
+// fills in pinned staging and copies over whole, so the copy also resets the
+// tile counter:
+//   BatchHeader | FrameDesc[nframes] | int32 tile_start[nframes + 1]
+//               | int32 nstrips[nframes]
+// tile_start is the prefix sum of tiles per frame, nstrips the tile columns
+// of each frame.  The kernel reads the counts from the header, so a captured
+// graph replays with new contents.
+struct BatchHeader {
+    int32_t counter;  // tile queue head: 0 in the staging, advanced by the kernel
+    int32_t pad0[31];  // the counter has a 128-byte cache line of its own
+    int32_t nframes, ntiles;
+    int32_t pad1[30];
+};
+static_assert(sizeof(BatchHeader) % alignof(FrameDesc) == 0, "frame table alignment");
+
+struct BatchTable {
+    BatchHeader *head;
+    FrameDesc *frames;
+    int32_t *tile_start;
+    int32_t *nstrips;
+};
+
+__host__ __device__ inline size_t batch_table_bytes(int64_t nframes) {
+    return sizeof(BatchHeader) + (size_t)nframes * sizeof(FrameDesc) +
+           (size_t)(2 * nframes + 1) * sizeof(int32_t);
+}
+
+__host__ __device__ inline BatchTable batch_table(void *base, int64_t nframes) {
+    BatchTable t;
+    t.head = static_cast<BatchHeader *>(base);
+    t.frames = reinterpret_cast<FrameDesc *>(t.head + 1);
+    t.tile_start = reinterpret_cast<int32_t *>(t.frames + nframes);
+    t.nstrips = t.tile_start + nframes + 1;
+    return t;
+}
+
+// Persistent grid pulling tiles from the table's counter.
 struct BatchArgs {
-    const FrameDesc *frames;   // [nframes]
-    const int32_t *tile_start; // [nframes + 1] prefix of tiles per frame
-    const int32_t *nstrips;    // [nframes]
-    const float4 *ktable;      // device-resident intrinsics (fx, fy, u0, v0)
-    int32_t *counter;          // tile queue head, 0 at launch
-    const int32_t *counts;     // if set: {nframes, ntiles} in device memory
-                               // (a captured graph replays with new counts)
-    int32_t nframes, ntiles, rows, chunk;
+    void *table;          // the block above, counter 0 at launch
+    const float4 *ktable; // device-resident intrinsics (fx, fy, u0, v0)
+    int32_t rows, chunk;
     float wa, wb;
 };
 

@@ -673,15 +673,17 @@ template <typename T> __device__ __forceinline__ T uniform_load(const T *p) {
 }
 
 // Persistent uneven batch: every wavefront pulls `chunk` consecutive tiles at
-// a time from a device counter until the queue is drained.
+// a time from the table's counter until the queue is drained.
 template <int KIND, bool FD, int AGG, int OUT, int PX, bool HALF>
 __global__ __launch_bounds__(kBlock) SNE_BATCH_OCCUPANCY void sne_batch_kernel(BatchArgs a) {
     const int lane = threadIdx.x & (kWave - 1);
-    const int nframes = a.counts ? uniform_load(a.counts) : a.nframes;
-    const int ntiles = a.counts ? uniform_load(a.counts + 1) : a.ntiles;
+    BatchHeader *head = static_cast<BatchHeader *>(a.table);
+    const int nframes = uniform_load(&head->nframes);
+    const int ntiles = uniform_load(&head->ntiles);
+    const BatchTable t = batch_table(a.table, nframes);
     for (;;) {
         int base = 0;
-        if (lane == 0) base = atomicAdd(a.counter, a.chunk);
+        if (lane == 0) base = atomicAdd(&head->counter, a.chunk);
         base = __builtin_amdgcn_readfirstlane(base);  // lane 0 is the first active lane
         if (base >= ntiles) return;
         const int end = min(base + a.chunk, ntiles);
@@ -690,17 +692,17 @@ __global__ __launch_bounds__(kBlock) SNE_BATCH_OCCUPANCY void sne_batch_kernel(B
             int lo = 0, hi = nframes - 1;
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
-                if (uniform_load(a.tile_start + mid) <= tile) lo = mid; else hi = mid - 1;
+                if (uniform_load(t.tile_start + mid) <= tile) lo = mid; else hi = mid - 1;
             }
             const int frame = lo;
-            FrameDesc f = uniform_load(a.frames + frame);
+            FrameDesc f = uniform_load(t.frames + frame);
             const float4 K = uniform_load(a.ktable + f.k_index);
             f.fx = K.x;
             f.fy = K.y;
             f.u0 = K.z;
             f.v0 = K.w;
-            const int local = tile - uniform_load(a.tile_start + frame);
-            const int ns = uniform_load(a.nstrips + frame);
+            const int local = tile - uniform_load(t.tile_start + frame);
+            const int ns = uniform_load(t.nstrips + frame);
             const int band = local / ns;
             const int strip = local - band * ns;
             const int r0 = band * a.rows * (HALF ? 2 : 1);

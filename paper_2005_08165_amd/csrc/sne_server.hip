@@ -7,9 +7,9 @@
 // slot's stream.  Batches on different slots run concurrently on the GPU;
 // requests that arrive meanwhile go into the next batch.  Each slot owns its
 // pinned descriptor staging, its device tables and (optionally) a captured
-// hipGraph per columns-per-lane class: {staging -> device copy, counter
-// reset, persistent kernel}; a batch rewrites the staging and replays the
-// graph.  Scheduling policy lives in sne_sched.cpp (pure C++).
+// hipGraph per columns-per-lane class: {staging -> device copy, persistent
+// kernel}; a batch rewrites the staging and replays the graph (the copy also
+// resets the kernel's tile counter).  Scheduling policy lives in sne_sched.cpp (pure C++).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,18 +30,12 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-struct Header {
-    int32_t nframes, ntiles;
-    int32_t pad[62];
-};
-
 struct SlotRes {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    void *h_stage = nullptr;   // pinned: Header | FrameDesc[cap] | start[cap+1] | nstrips[cap]
-    void *d_stage = nullptr;   // device mirror
-    int32_t *d_counter = nullptr;
-    size_t bytes = 0;
+    void *h_stage = nullptr;   // pinned batch table (layout: BatchTable)
+    void *d_stage = nullptr;   // device copy
+    size_t bytes = 0;          // table size at full capacity
     hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};  // px = 1, 2, 4
     const void *graph_ktable = nullptr;
     bool launched = false;
@@ -59,24 +53,19 @@ public:
     size_t cap = 0;
     int rows = 16;
 
-    size_t off_frames() const { return sizeof(Header); }
-    size_t off_start() const { return off_frames() + cap * sizeof(FrameDesc); }
-    size_t off_ns() const { return off_start() + (cap + 1) * sizeof(int32_t); }
-
     int init(sne_ctx *c, const sne_server_config &conf, uint8_t *arena_base) {
         ctx = c;
         cfg = conf;
         arena = arena_base;
         cap = (size_t)cfg.max_batch_frames;
         slots.resize(cfg.max_inflight);
-        const size_t bytes = off_ns() + cap * sizeof(int32_t);
+        const size_t bytes = batch_table_bytes((int64_t)cap);
         for (auto &s : slots) {
             s.bytes = bytes;
             if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
                 hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess ||
                 hipHostMalloc(&s.h_stage, bytes, hipHostMallocDefault) != hipSuccess ||
-                hipMalloc(&s.d_stage, bytes) != hipSuccess ||
-                hipMalloc(&s.d_counter, sizeof(int32_t)) != hipSuccess)
+                hipMalloc(&s.d_stage, bytes) != hipSuccess)
                 return SNE_ERR_HIP;
             std::memset(s.h_stage, 0, bytes);
         }
@@ -92,22 +81,14 @@ public:
             if (s.stream) (void)hipStreamDestroy(s.stream);
             if (s.h_stage) (void)hipHostFree(s.h_stage);
             if (s.d_stage) (void)hipFree(s.d_stage);
-            if (s.d_counter) (void)hipFree(s.d_counter);
         }
         slots.clear();
     }
 
     BatchArgs args(SlotRes &s) const {
         BatchArgs a;
-        uint8_t *d = (uint8_t *)s.d_stage;
-        a.frames = (const FrameDesc *)(d + off_frames());
-        a.tile_start = (const int32_t *)(d + off_start());
-        a.nstrips = (const int32_t *)(d + off_ns());
+        a.table = s.d_stage;
         a.ktable = reinterpret_cast<const float4 *>(ctx->d_K);
-        a.counter = s.d_counter;
-        a.counts = (const int32_t *)d;  // Header.nframes, Header.ntiles
-        a.nframes = 0;
-        a.ntiles = 0;
         a.rows = rows;
         a.chunk = 1;
         grad_weights(cfg.grad, a.wa, a.wb);
@@ -119,12 +100,13 @@ public:
         return ctx->num_cu * occ;
     }
 
-    // The steps of one batch, enqueued on the slot's stream.
-    hipError_t enqueue(SlotRes &s, int px) {
-        hipError_t e = hipMemcpyAsync(s.d_stage, s.h_stage, s.bytes, hipMemcpyHostToDevice,
+    // The steps of one batch, enqueued on the slot's stream: the table copy
+    // (`bytes` of it; a captured graph copies the whole capacity) and the
+    // persistent kernel.
+    hipError_t enqueue(SlotRes &s, int px, size_t bytes) {
+        hipError_t e = hipMemcpyAsync(s.d_stage, s.h_stage, bytes, hipMemcpyHostToDevice,
                                       s.stream);
         if (e != hipSuccess) return e;
-        if ((e = launch_zero_counter(s.d_counter, s.stream)) != hipSuccess) return e;
         Variant v{cfg.kind, cfg.grad, cfg.agg, cfg.out_type, px};
         return launch_batch(v, args(s), grid(), s.stream);
     }
@@ -134,7 +116,7 @@ public:
         hipGraphExec_t ex = nullptr;
         if (hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return SNE_ERR_HIP;
-        const hipError_t e = enqueue(s, px);
+        const hipError_t e = enqueue(s, px, s.bytes);
         const hipError_t e2 = hipStreamEndCapture(s.stream, &g);
         if (e != hipSuccess || e2 != hipSuccess || !g) {
             if (g) (void)hipGraphDestroy(g);
@@ -149,10 +131,8 @@ public:
 
     int launch(sched::Batch &b) override {
         SlotRes &s = slots[b.slot];
-        Header *h = (Header *)s.h_stage;
-        FrameDesc *fd = (FrameDesc *)((uint8_t *)s.h_stage + off_frames());
-        int32_t *start = (int32_t *)((uint8_t *)s.h_stage + off_start());
-        int32_t *ns = (int32_t *)((uint8_t *)s.h_stage + off_ns());
+        const int64_t nb = (int64_t)b.reqs.size();
+        const BatchTable bt = batch_table(s.h_stage, nb);
         const size_t oe = out_elem(cfg.out_type);
         int px = 4;
         for (auto *q : b.reqs) {
@@ -162,22 +142,24 @@ public:
                                      (int64_t)q->H * q->W, cfg.kind, cfg.out_type));
         }
         int64_t tiles = 0;
-        for (size_t i = 0; i < b.reqs.size(); ++i) {
+        for (int64_t i = 0; i < nb; ++i) {
             auto *q = b.reqs[i];
             uint8_t *out = arena + q->out_offset;
             uint8_t *mask = out + 3 * (size_t)q->H * q->W * oe;
             const sne_intrinsics unused{1.f, 1.f, 0.f, 0.f};  // the kernel reads the table
-            fd[i] = make_desc(q->in, out, mask, q->H, q->W, q->in_pitch, q->W, q->W, unused);
-            fd[i].k_index = q->stream;
+            bt.frames[i] = make_desc(q->in, out, mask, q->H, q->W, q->in_pitch, q->W, q->W,
+                                     unused);
+            bt.frames[i].k_index = q->stream;
             const int nst = (q->W + 64 * px - 1) / (64 * px);
-            const int nb = (q->H + rows - 1) / rows;
-            start[i] = (int32_t)tiles;
-            ns[i] = nst;
-            tiles += (int64_t)nst * nb;
+            const int nbands = (q->H + rows - 1) / rows;
+            bt.tile_start[i] = (int32_t)tiles;
+            bt.nstrips[i] = nst;
+            tiles += (int64_t)nst * nbands;
         }
-        start[b.reqs.size()] = (int32_t)tiles;
-        h->nframes = (int32_t)b.reqs.size();
-        h->ntiles = (int32_t)tiles;
+        bt.tile_start[nb] = (int32_t)tiles;
+        *bt.head = BatchHeader{};
+        bt.head->nframes = (int32_t)nb;
+        bt.head->ntiles = (int32_t)tiles;
         hipSetDevice(ctx->device);
         hipError_t e;
         if (cfg.use_graphs) {
@@ -193,7 +175,7 @@ public:
             }
             e = hipGraphLaunch(s.graph[px_index(px)], s.stream);
         } else {
-            e = enqueue(s, px);
+            e = enqueue(s, px, batch_table_bytes(nb));
         }
         if (e != hipSuccess || hipEventRecord(s.done, s.stream) != hipSuccess) return SNE_ERR_HIP;
         s.launched = true;
