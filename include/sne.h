@@ -173,9 +173,11 @@ int sne_get_tile(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int gr
                  int out_type, sne_tile *tile);
 
 /* Time every candidate tile shape on an H x W x B workload of this variant
- * (synthetic planar input in scratch buffers the call allocates and frees),
- * keep the fastest in ctx's cache for the frame-size class of H x W, and
- * report it (tile may be NULL).  Synchronous; seconds at most. */
+ * (synthetic planar input in scratch buffers the call allocates and frees;
+ * up to 8 copies of the input, at least 512 MB together, are used in turn so
+ * that launches read from HBM rather than the last-level cache), keep the
+ * fastest in ctx's cache for the frame-size class of H x W, and report it
+ * (tile may be NULL).  Synchronous; seconds at most. */
 int sne_autotune(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int grad, int agg,
                  int out_type, sne_tile *tile);
 

@@ -448,12 +448,17 @@ int sne_autotune(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int gr
         return SNE_ERR_ARG;
     hipSetDevice(ctx->device);
     const int64_t npx = (int64_t)B * H * W;
+    // The input is a ring of copies that together exceed the last-level
+    // cache (256 MB), so a timed launch reads its input from HBM as it
+    // would in use, not from the copy the previous launch left in cache.
+    const int64_t in_bytes = npx * (int64_t)in_elem(kind);
+    const int ncopy = (int)std::min<int64_t>(8, std::max<int64_t>(1, ((512ll << 20) + in_bytes - 1) / in_bytes));
     void *in = nullptr, *out = nullptr;
     uint8_t *mask = nullptr;
     hipStream_t st = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = SNE_OK;
-    if (hipMalloc(&in, npx * in_elem(kind)) != hipSuccess ||
+    if (hipMalloc(&in, ncopy * in_bytes) != hipSuccess ||
         hipMalloc(&out, 3 * npx * out_elem(out_type)) != hipSuccess ||
         hipMalloc(&mask, npx) != hipSuccess || hipStreamCreate(&st) != hipSuccess ||
         hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -462,13 +467,14 @@ int sne_autotune(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int gr
     TileChoice best{0, 0, 0, 0};
     if (rc == SNE_OK) {
         const int threads = 256;
-        const int blocks = (int)((npx + threads - 1) / threads);
+        const int64_t nfill = ncopy * npx;
+        const int blocks = (int)((nfill + threads - 1) / threads);
         if (kind == SNE_DEPTH_F32 || kind == SNE_DISPARITY_F32)
             hipLaunchKernelGGL(fill_pattern<float>, dim3(blocks), dim3(threads), 0, st,
-                               (float *)in, npx, W, kind);
+                               (float *)in, nfill, W, kind);
         else
             hipLaunchKernelGGL(fill_pattern<uint16_t>, dim3(blocks), dim3(threads), 0, st,
-                               (uint16_t *)in, npx, W, kind);
+                               (uint16_t *)in, nfill, W, kind);
         sne_intrinsics K{(float)W, (float)W, (W - 1) * 0.5f, (H - 1) * 0.5f};
         const int pxmax = max_px(in, out, mask, W, W, W, W, (int64_t)H * W, 3LL * H * W,
                                  (int64_t)H * W, (int64_t)H * W, kind, out_type);
@@ -476,7 +482,9 @@ int sne_autotune(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int gr
         // launch); the eight fastest are then timed again in interleaved
         // rounds, so that a slow phase of the device does not favour
         // whichever candidate ran during it, and the median round decides.
-        const int rows_set[] = {2, 4, 8, 16, 32, 64};
+        // powers of two plus in-between heights: the number of tiles decides
+        // how the last round of wavefronts fills the GPU
+        const int rows_set[] = {2, 4, 6, 8, 10, 12, 16, 20, 24, 32, 64};
         std::vector<TileChoice> cand;
         for (int px : {1, 2, 4}) {
             if (px > pxmax) continue;
@@ -485,23 +493,32 @@ int sne_autotune(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int gr
                 for (int tk = 0; tk < 4; ++tk) cand.push_back(TileChoice{px, rows, tk & 1, tk >> 1});
             }
         }
+        int next_copy = 0;
+        auto launch = [&](const TileChoice &t) -> bool {
+            const void *src = static_cast<const char *>(in) + next_copy * in_bytes;
+            next_copy = (next_copy + 1) % ncopy;
+            return uniform_impl(ctx, src, B, H, W, W, (int64_t)H * W, &K, kind, grad, agg,
+                                out_type, out, W, 3LL * H * W, mask, W, (int64_t)H * W, st,
+                                &t) == SNE_OK;
+        };
+        int burst = 3;  // launches per timing, sized below to about 2 ms
         auto time_one = [&](const TileChoice &t, float &ms) -> bool {
-            constexpr int kBurst = 3;
-            if (uniform_impl(ctx, in, B, H, W, W, (int64_t)H * W, &K, kind, grad, agg, out_type,
-                             out, W, 3LL * H * W, mask, W, (int64_t)H * W, st, &t) != SNE_OK)
-                return false;
+            if (!launch(t)) return false;  // warm-up
             hipEventRecord(e0, st);
-            for (int i = 0; i < kBurst; ++i)
-                if (uniform_impl(ctx, in, B, H, W, W, (int64_t)H * W, &K, kind, grad, agg,
-                                 out_type, out, W, 3LL * H * W, mask, W, (int64_t)H * W, st,
-                                 &t) != SNE_OK)
-                    return false;
+            for (int i = 0; i < burst; ++i)
+                if (!launch(t)) return false;
             hipEventRecord(e1, st);
             if (hipEventSynchronize(e1) != hipSuccess) return false;
             hipEventElapsedTime(&ms, e0, e1);
-            ms /= kBurst;
+            ms /= burst;
             return true;
         };
+        {
+            float ms = 0.f;
+            const TileChoice t0 = default_tile(ctx, H, W, B, pxmax);
+            if (time_one(t0, ms) && ms > 0.f)
+                burst = (int)std::min(64.f, std::max(3.f, std::ceil(2.0f / ms)));
+        }
         std::vector<std::pair<float, size_t>> first;
         for (size_t i = 0; i < cand.size(); ++i) {
             float ms;
@@ -509,7 +526,7 @@ int sne_autotune(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int gr
         }
         std::sort(first.begin(), first.end());
         if (first.size() > 8) first.resize(8);
-        constexpr int kRounds = 5;
+        constexpr int kRounds = 7;
         std::vector<std::vector<float>> rounds(first.size());
         for (int r = 0; r < kRounds; ++r)
             for (size_t j = 0; j < first.size(); ++j) {

@@ -22,8 +22,9 @@ WORKLOADS = [
     (480, 640, 64, "depth_f32", "sobel", "median", "f32"),
     (480, 640, 64, "depth_f32", "fd", "mean", "f32"),
     (480, 640, 1, "depth_f32", "sobel", "median", "f32"),
-    (375, 1242, 128, "disparity_f32", "sobel", "median", "f32"),
+    (375, 1242, 128, "disparity_f32", "scharr", "median", "f32"),
     (1080, 1920, 64, "depth_u16", "fd", "median", "f16"),
+    (1080, 1920, 64, "depth_u16", "fd", "mean", "f16"),
     (1080, 1920, 1, "depth_u16", "fd", "median", "f16"),
 ]
 
