@@ -152,7 +152,7 @@ def uneven_batch(torch, S, sne, agg, n_frames=1024, reps=5, autotune=False):
             "frames_per_s": round(n_frames * reps / ev, 1),
             "achieved_GBs": round(px * 9 * reps / ev / 1e9, 1),
             "frac_of_peak": round(px * 9 * reps / ev / 1e9 / PEAK_HBM_GBS, 4),
-            "note": "event time per call: table copy (it also resets the tile counter) + kernel"}
+            "note": "event time per call: table copy (it also resets the tile queues) + kernel"}
 
 
 def serving(torch, S, sne, duration=2.0, slo_p99_ms=2.0, plain_run=True,

@@ -277,7 +277,7 @@ int batched_impl(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int
     bt.head->nframes = n;
     bt.head->ntiles = (int32_t)tiles;
     hipStream_t st = (hipStream_t)stream;
-    // one copy of the used part of the table; it also zeroes the tile counter
+    // one copy of the used part of the table; it also zeroes the tile queues
     if (hipMemcpyAsync(s.d_table, s.h_stage, batch_table_bytes(n), hipMemcpyHostToDevice, st) !=
         hipSuccess)
         return SNE_ERR_HIP;

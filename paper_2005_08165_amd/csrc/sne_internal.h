@@ -37,17 +37,26 @@ struct UniformArgs {
 
 // Uneven batch.  Its tables are one block of device memory that the host
 // fills in pinned staging and copies over whole, so the copy also resets the
-// tile counter:
+// tile queues:
 //   BatchHeader | FrameDesc[nframes] | int32 tile_start[nframes + 1]
 //               | int32 nstrips[nframes]
 // tile_start is the prefix sum of tiles per frame, nstrips the tile columns
 // of each frame.  The kernel reads the counts from the header, so a captured
 // graph replays with new contents.
+//
+// The tiles are split into kQueues contiguous ranges, one per XCD; queue x
+// hands out the tiles of range x to the wavefronts of blocks b with
+// b % kQueues == x (the blocks the dispatcher places on XCD x), which then
+// help drain the other queues.  Each head has a 128-byte line of its own.
+constexpr int kQueues = 8;
+struct alignas(128) TileQueue {
+    int32_t next;  // tiles taken from the range so far: 0 in the staging
+    int32_t pad[31];
+};
 struct BatchHeader {
-    int32_t counter;  // tile queue head: 0 in the staging, advanced by the kernel
-    int32_t pad0[31];  // the counter has a 128-byte cache line of its own
+    TileQueue queue[kQueues];
     int32_t nframes, ntiles;
-    int32_t pad1[30];
+    int32_t pad[30];
 };
 static_assert(sizeof(BatchHeader) % alignof(FrameDesc) == 0, "frame table alignment");
 
@@ -72,9 +81,9 @@ __host__ __device__ inline BatchTable batch_table(void *base, int64_t nframes) {
     return t;
 }
 
-// Persistent grid pulling tiles from the table's counter.
+// Persistent grid pulling tiles from the table's queues.
 struct BatchArgs {
-    void *table;          // the block above, counter 0 at launch
+    void *table;          // the block above, queue heads 0 at launch
     const float4 *ktable; // device-resident intrinsics (fx, fy, u0, v0)
     int32_t rows, chunk;
     float wa, wb;

@@ -672,8 +672,32 @@ template <typename T> __device__ __forceinline__ T uniform_load(const T *p) {
     return __builtin_bit_cast(T, v);
 }
 
-// Persistent uneven batch: every wavefront pulls `chunk` consecutive tiles at
-// a time from the table's counter until the queue is drained.
+// Frame of a tile: the last f with tile_start[f] <= tile (tile_start is
+// strictly increasing, tile_start[0] = 0).  The 64 lanes probe evenly spaced
+// frames of the remaining range at once and a ballot keeps the segment that
+// holds the tile, so 1024 frames take two dependent loads instead of the ten
+// of a binary search.  Called with all lanes active.
+__device__ __forceinline__ int find_frame(const int32_t *tile_start, int nframes, int tile) {
+    const int lane = threadIdx.x & (kWave - 1);
+    int lo = 0, hi = nframes - 1;  // the frame is in [lo, hi]; tile_start[lo] <= tile
+    while (lo < hi) {
+        const int step = (hi - lo + kWave) / kWave;  // ceil((hi - lo + 1) / 64)
+        const int probe = lo + lane * step;
+        const int32_t v = tile_start[min(probe, hi)];  // in bounds for every lane
+        const bool le = probe <= hi && v <= tile;
+        const uint64_t m = __builtin_amdgcn_ballot_w64(le);  // lanes 0..k, k >= 0
+        const int k = 63 - __builtin_clzll(m);
+        lo += k * step;
+        hi = min(hi, lo + step - 1);
+    }
+    return lo;
+}
+
+// Persistent uneven batch.  A wavefront first takes `chunk` tiles at a time
+// from the queue of its block's XCD, then from the other queues in turn,
+// until all are drained.  The queues hold contiguous tile ranges, so
+// neighbouring tiles (which share halo rows) mostly run on one XCD and meet
+// in its L2, and the atomic increments are spread over eight addresses.
 template <int KIND, bool FD, int AGG, int OUT, int PX, bool HALF>
 __global__ __launch_bounds__(kBlock) SNE_BATCH_OCCUPANCY void sne_batch_kernel(BatchArgs a) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -681,33 +705,35 @@ __global__ __launch_bounds__(kBlock) SNE_BATCH_OCCUPANCY void sne_batch_kernel(B
     const int nframes = uniform_load(&head->nframes);
     const int ntiles = uniform_load(&head->ntiles);
     const BatchTable t = batch_table(a.table, nframes);
-    for (;;) {
-        int base = 0;
-        if (lane == 0) base = atomicAdd(&head->counter, a.chunk);
-        base = __builtin_amdgcn_readfirstlane(base);  // lane 0 is the first active lane
-        if (base >= ntiles) return;
-        const int end = min(base + a.chunk, ntiles);
-        for (int tile = base; tile < end; ++tile) {
-            // frame = last index with tile_start[frame] <= tile
-            int lo = 0, hi = nframes - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (uniform_load(t.tile_start + mid) <= tile) lo = mid; else hi = mid - 1;
+    const int home = (int)(blockIdx.x % kQueues);
+    for (int i = 0; i < kQueues; ++i) {
+        const int q = (home + i) % kQueues;
+        const int begin = (int)((int64_t)ntiles * q / kQueues);
+        const int end = (int)((int64_t)ntiles * (q + 1) / kQueues);
+        for (;;) {
+            int taken = 0;
+            if (lane == 0) taken = atomicAdd(&head->queue[q].next, a.chunk);
+            taken = __builtin_amdgcn_readfirstlane(taken);  // lane 0 is the first active lane
+            const int first = begin + min(taken, end - begin);
+            if (first >= end) break;
+            const int last = min(first + a.chunk, end);
+            for (int tile = first; tile < last; ++tile) {
+                const int frame =
+                    __builtin_amdgcn_readfirstlane(find_frame(t.tile_start, nframes, tile));
+                FrameDesc f = uniform_load(t.frames + frame);
+                const float4 K = uniform_load(a.ktable + f.k_index);
+                f.fx = K.x;
+                f.fy = K.y;
+                f.u0 = K.z;
+                f.v0 = K.w;
+                const int local = tile - uniform_load(t.tile_start + frame);
+                const int ns = uniform_load(t.nstrips + frame);
+                const int band = local / ns;
+                const int strip = local - band * ns;
+                const int r0 = band * a.rows * (HALF ? 2 : 1);
+                run_tile<KIND, FD, AGG, OUT, PX, HALF>(f, strip * (HALF ? kWave / 2 : kWave) * PX,
+                                                       r0, a.rows, a.wa, a.wb);
             }
-            const int frame = lo;
-            FrameDesc f = uniform_load(t.frames + frame);
-            const float4 K = uniform_load(a.ktable + f.k_index);
-            f.fx = K.x;
-            f.fy = K.y;
-            f.u0 = K.z;
-            f.v0 = K.w;
-            const int local = tile - uniform_load(t.tile_start + frame);
-            const int ns = uniform_load(t.nstrips + frame);
-            const int band = local / ns;
-            const int strip = local - band * ns;
-            const int r0 = band * a.rows * (HALF ? 2 : 1);
-            run_tile<KIND, FD, AGG, OUT, PX, HALF>(f, strip * (HALF ? kWave / 2 : kWave) * PX, r0,
-                                                   a.rows, a.wa, a.wb);
         }
     }
 }

@@ -9,7 +9,8 @@
 // pinned descriptor staging, its device tables and (optionally) a captured
 // hipGraph per columns-per-lane class: {staging -> device copy, persistent
 // kernel}; a batch rewrites the staging and replays the graph (the copy also
-// resets the kernel's tile counter).  Scheduling policy lives in sne_sched.cpp (pure C++).
+// resets the kernel's tile queues).  Scheduling policy lives in sne_sched.cpp
+// (pure C++).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
