@@ -126,23 +126,16 @@ def uneven_batch(torch, S, sne, agg, n_frames=1024, reps=5, autotune=False):
     """One persistent launch over n_frames frames of sizes drawn uniformly
     from {240x320, 480x640, 720x1280, 1080x1920}: uint16 millimetre depth in,
     FP16 normals + mask out (9 B/px), FD gradients, tile shape from the
-    shipped tuning table (or tuned live)."""
-    shapes = S.uneven_sizes(n_frames, seed=3999)
-    uniq = sorted(set(shapes))
-    ctx = sne.Context(0)
-    cams = {sh: S.camera_for(*sh) for sh in uniq}
-    ctx.set_intrinsics_table([cams[sh].as_tuple() for sh in uniq])
-    kidx = {sh: i for i, sh in enumerate(uniq)}
+    shipped tuning table (or tuned live on this batch)."""
     # 16 distinct scenes per size, reused across the batch (inputs stay resident)
-    pool = {sh: [S.make_u16(4000 + 97 * j + i, cams[sh], device="cuda").raw for j in range(16)]
-            for i, sh in enumerate(uniq)}
-    frames = [pool[sh][k % 16] for k, sh in enumerate(shapes)]
+    shapes, Ks, ki, frames = S.uneven_batch(n_frames, seed=3999, device="cuda")
+    ctx = sne.Context(0)
+    ctx.set_intrinsics_table(Ks)
     nrm = [torch.empty((3,) + sh, dtype=torch.float16, device="cuda") for sh in shapes]
     msk = [torch.empty(sh, dtype=torch.uint8, device="cuda") for sh in shapes]
-    if autotune:
-        ctx.autotune(1080, 1920, 64, "depth_u16", "fd", agg, "f16")
-    ki = [kidx[sh] for sh in shapes]
     descs, _, _ = ctx.prepare_batched(frames, ki, "depth_u16", "f16", nrm, msk)
+    if autotune:
+        ctx.autotune_batched(descs, "depth_u16", "fd", agg, "f16")
     wall, ev = time_launches(torch, lambda i: ctx.run_batched(descs, "depth_u16", "fd", agg, "f16"),
                              2, reps)
     px = sum(h * w for h, w in shapes)
@@ -349,8 +342,8 @@ def main():
                                      plain_single_frame(torch, S, sne, "fd", "mean")]
     if not args.no_uneven:
         log("uneven persistent batch")
-        res["uneven_batch"] = [uneven_batch(torch, S, sne, "mean"),
-                               uneven_batch(torch, S, sne, "median")]
+        res["uneven_batch"] = [uneven_batch(torch, S, sne, "mean", autotune=args.autotune),
+                               uneven_batch(torch, S, sne, "median", autotune=args.autotune)]
     if not args.no_serving:
         log("serving loop")
         if args.serving_rate > 0:

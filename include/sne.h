@@ -174,12 +174,22 @@ int sne_get_tile(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int gr
 
 /* Time every candidate tile shape on an H x W x B workload of this variant
  * (synthetic planar input in scratch buffers the call allocates and frees;
- * up to 8 copies of the input, at least 512 MB together, are used in turn so
- * that launches read from HBM rather than the last-level cache), keep the
+ * up to 8 sets of input and outputs, at least 1 GB together, are used in turn
+ * so that launches read and write HBM rather than the last-level cache), keep the
  * fastest in ctx's cache for the frame-size class of H x W, and report it
  * (tile may be NULL).  Synchronous; seconds at most. */
 int sne_autotune(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int grad, int agg,
                  int out_type, sne_tile *tile);
+
+/* Time every candidate tile shape on the caller's uneven batch (the frames
+ * of sne_estimate_batched, whose outputs are written by every timed launch;
+ * the results are the same for every shape), keep the fastest in ctx's cache
+ * for uneven batches of this largest frame size, which sne_estimate_batched
+ * then prefers to the shape tuned on uniform batches, and report it (tile may
+ * be NULL).  Same argument checks as sne_estimate_batched; n >= 1.
+ * Synchronous; seconds at most. */
+int sne_autotune_batched(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int grad,
+                         int agg, int out_type, sne_tile *tile);
 
 /* Save / load the tile-shape cache as text.  Entries recorded for another
  * GPU architecture or library version are ignored on load. */

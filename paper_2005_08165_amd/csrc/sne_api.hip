@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <vector>
 
 
@@ -89,18 +90,23 @@ TileChoice default_tile(const sne_ctx *ctx, int H, int W, int64_t B, int pxmax) 
     return best;
 }
 
-TileChoice pick_tile(const sne_ctx *ctx, int H, int W, int64_t B, const Variant &v, int pxmax) {
+TileChoice pick_tile(const sne_ctx *ctx, int H, int W, int64_t B, const Variant &v, int pxmax,
+                     bool uneven) {
     if (ctx && ctx->forced.rows > 0) {
         TileChoice t = ctx->forced;
         while (t.px > pxmax) t.px >>= 1;
         return t;
     }
     if (ctx) {
-        auto it = ctx->cache.find(TileKey{H, W, batch_class(B), v.kind, v.grad, v.agg, v.out});
-        if (it != ctx->cache.end()) {
-            TileChoice t = it->second;
-            while (t.px > pxmax) t.px >>= 1;
-            return t;
+        // an uneven batch prefers a shape tuned on the persistent kernel
+        for (int bc : {uneven ? kUnevenClass : -1, batch_class(B)}) {
+            if (bc < 0) continue;
+            auto it = ctx->cache.find(TileKey{H, W, bc, v.kind, v.grad, v.agg, v.out});
+            if (it != ctx->cache.end()) {
+                TileChoice t = it->second;
+                while (t.px > pxmax) t.px >>= 1;
+                return t;
+            }
         }
     }
     return default_tile(ctx, H, W, B, pxmax);
@@ -224,14 +230,12 @@ int ensure_slot(Slot &s, size_t n) {
     return SNE_OK;
 }
 
-int batched_impl(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int grad, int agg,
-                 int out_type, void *stream, const TileChoice *force) {
-    if (!ctx || n < 0 || !valid_enum(kind, grad, agg, out_type)) return SNE_ERR_ARG;
-    if (n == 0) return SNE_OK;  // an empty batch: frames may be NULL
-    if (!frames) return SNE_ERR_ARG;
-    // validate every descriptor before touching the GPU
-    int pxmax = 4;
-    int maxH = 0, maxW = 0;
+// Validate every descriptor of an uneven batch (before anything touches the
+// GPU) and find the largest frame and the widest vector width all allow.
+int scan_batch(const sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int out_type,
+               int &maxH, int &maxW, int &pxmax) {
+    pxmax = 4;
+    maxH = maxW = 0;
     for (int32_t i = 0; i < n; ++i) {
         const sne_frame &f = frames[i];
         if (!f.in || !f.normals || f.H < 1 || f.W < 1 || f.in_pitch < f.W ||
@@ -246,8 +250,19 @@ int batched_impl(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int
         maxH = std::max(maxH, (int)f.H);
         maxW = std::max(maxW, (int)f.W);
     }
+    return SNE_OK;
+}
+
+int batched_impl(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int grad, int agg,
+                 int out_type, void *stream, const TileChoice *force) {
+    if (!ctx || n < 0 || !valid_enum(kind, grad, agg, out_type)) return SNE_ERR_ARG;
+    if (n == 0) return SNE_OK;  // an empty batch: frames may be NULL
+    if (!frames) return SNE_ERR_ARG;
+    int pxmax = 4, maxH = 0, maxW = 0;
+    const int rc0 = scan_batch(ctx, frames, n, kind, out_type, maxH, maxW, pxmax);
+    if (rc0 != SNE_OK) return rc0;
     Variant v{kind, grad, agg, out_type, 1};
-    TileChoice t = force ? *force : pick_tile(ctx, maxH, maxW, n, v, pxmax);
+    TileChoice t = force ? *force : pick_tile(ctx, maxH, maxW, n, v, pxmax, true);
     if (t.px > pxmax || t.rows < 1) return SNE_ERR_ARG;
     v.px = kernel_px(t);
     Slot &s = ctx->slots[ctx->next_slot];
@@ -313,6 +328,87 @@ __global__ void fill_pattern(T *p, int64_t n, int W, int kind) {
         p[i] = (T)(40.f / val);
     else
         p[i] = (T)val;
+}
+
+
+// Candidate tile shapes: powers of two plus in-between heights (the number of
+// tiles decides how the last round of wavefronts fills the GPU).  The
+// persistent kernel has its own XCD queues, so the block-order remap is not a
+// candidate there.
+std::vector<TileChoice> tile_candidates(int H, int pxmax, bool remap_choices) {
+    const int rows_set[] = {2, 4, 6, 8, 10, 12, 16, 20, 24, 32, 64};
+    std::vector<TileChoice> cand;
+    for (int px : {1, 2, 4}) {
+        if (px > pxmax) continue;
+        for (int rows : rows_set) {
+            if (rows > 2 * H) continue;
+            for (int half : {0, 1})
+                for (int remap = 0; remap <= (remap_choices ? 1 : 0); ++remap)
+                    cand.push_back(TileChoice{px, rows, remap, half});
+        }
+    }
+    return cand;
+}
+
+// Every candidate is timed once (a burst of launches of about 2 ms after a
+// warm-up launch); the eight fastest are then timed again in interleaved
+// rounds, so that a slow phase of the device does not favour whichever
+// candidate ran during it, and the best median wins.  `launch` enqueues one
+// launch of a shape on `st`.  Returns rows = 0 if nothing could be timed.
+TileChoice pick_fastest(const std::vector<TileChoice> &cand, const TileChoice &probe,
+                        const std::function<bool(const TileChoice &)> &launch, hipStream_t st,
+                        hipEvent_t e0, hipEvent_t e1) {
+    int burst = 3;
+    auto time_one = [&](const TileChoice &t, float &ms) -> bool {
+        if (!launch(t)) return false;  // warm-up
+        hipEventRecord(e0, st);
+        for (int i = 0; i < burst; ++i)
+            if (!launch(t)) return false;
+        hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess) return false;
+        hipEventElapsedTime(&ms, e0, e1);
+        ms /= burst;
+        return true;
+    };
+    {
+        float ms = 0.f;
+        if (time_one(probe, ms) && ms > 0.f)
+            burst = (int)std::min(64.f, std::max(3.f, std::ceil(2.0f / ms)));
+    }
+    std::vector<std::pair<float, size_t>> first;
+    for (size_t i = 0; i < cand.size(); ++i) {
+        float ms;
+        if (time_one(cand[i], ms)) first.emplace_back(ms, i);
+    }
+    std::sort(first.begin(), first.end());
+    if (first.size() > 8) first.resize(8);
+    constexpr int kRounds = 7;
+    std::vector<std::vector<float>> rounds(first.size());
+    for (int r = 0; r < kRounds; ++r)
+        for (size_t j = 0; j < first.size(); ++j) {
+            float ms;
+            if (time_one(cand[first[j].second], ms)) rounds[j].push_back(ms);
+        }
+    TileChoice best{0, 0, 0, 0};
+    float best_ms = 1e30f;
+    for (size_t j = 0; j < first.size(); ++j) {
+        std::vector<float> &v = rounds[j];
+        if (v.empty()) continue;
+        std::sort(v.begin(), v.end());
+        const float med = v[v.size() / 2];
+        if (med < best_ms) {
+            best_ms = med;
+            best = cand[first[j].second];
+        }
+    }
+    return best;
+}
+
+void report_tile(const TileChoice &t, sne_tile *tile) {
+    if (!tile) return;
+    tile->cols_per_lane = t.px;
+    tile->rows = t.rows;
+    tile->lanes = t.half ? 32 : 64;
 }
 
 }  // namespace
@@ -442,32 +538,37 @@ int sne_get_tile(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int gr
     return SNE_OK;
 }
 
+
 int sne_autotune(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int grad, int agg,
                  int out_type, sne_tile *tile) {
     if (!ctx || H < 1 || W < 1 || B < 1 || !valid_enum(kind, grad, agg, out_type))
         return SNE_ERR_ARG;
     hipSetDevice(ctx->device);
     const int64_t npx = (int64_t)B * H * W;
-    // The input is a ring of copies that together exceed the last-level
-    // cache (256 MB), so a timed launch reads its input from HBM as it
-    // would in use, not from the copy the previous launch left in cache.
+    // Inputs and outputs form a ring of sets that together exceed the
+    // last-level cache (256 MB) several times, so a timed launch reads and
+    // writes HBM as it would in use, not lines the previous launch left in
+    // cache.
     const int64_t in_bytes = npx * (int64_t)in_elem(kind);
-    const int ncopy = (int)std::min<int64_t>(8, std::max<int64_t>(1, ((512ll << 20) + in_bytes - 1) / in_bytes));
+    const int64_t out_bytes = 3 * npx * (int64_t)out_elem(out_type);
+    const int64_t set_bytes = in_bytes + out_bytes + npx;
+    const int nset = (int)std::min<int64_t>(
+        8, std::max<int64_t>(1, ((1ll << 30) + set_bytes - 1) / set_bytes));
     void *in = nullptr, *out = nullptr;
     uint8_t *mask = nullptr;
     hipStream_t st = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = SNE_OK;
-    if (hipMalloc(&in, ncopy * in_bytes) != hipSuccess ||
-        hipMalloc(&out, 3 * npx * out_elem(out_type)) != hipSuccess ||
-        hipMalloc(&mask, npx) != hipSuccess || hipStreamCreate(&st) != hipSuccess ||
+    if (hipMalloc(&in, nset * in_bytes) != hipSuccess ||
+        hipMalloc(&out, nset * out_bytes) != hipSuccess ||
+        hipMalloc(&mask, nset * npx) != hipSuccess || hipStreamCreate(&st) != hipSuccess ||
         hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         rc = SNE_ERR_HIP;
     }
     TileChoice best{0, 0, 0, 0};
     if (rc == SNE_OK) {
         const int threads = 256;
-        const int64_t nfill = ncopy * npx;
+        const int64_t nfill = nset * npx;
         const int blocks = (int)((nfill + threads - 1) / threads);
         if (kind == SNE_DEPTH_F32 || kind == SNE_DISPARITY_F32)
             hipLaunchKernelGGL(fill_pattern<float>, dim3(blocks), dim3(threads), 0, st,
@@ -478,72 +579,18 @@ int sne_autotune(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int gr
         sne_intrinsics K{(float)W, (float)W, (W - 1) * 0.5f, (H - 1) * 0.5f};
         const int pxmax = max_px(in, out, mask, W, W, W, W, (int64_t)H * W, 3LL * H * W,
                                  (int64_t)H * W, (int64_t)H * W, kind, out_type);
-        // Every candidate is timed once (a burst of launches after a warm-up
-        // launch); the eight fastest are then timed again in interleaved
-        // rounds, so that a slow phase of the device does not favour
-        // whichever candidate ran during it, and the median round decides.
-        // powers of two plus in-between heights: the number of tiles decides
-        // how the last round of wavefronts fills the GPU
-        const int rows_set[] = {2, 4, 6, 8, 10, 12, 16, 20, 24, 32, 64};
-        std::vector<TileChoice> cand;
-        for (int px : {1, 2, 4}) {
-            if (px > pxmax) continue;
-            for (int rows : rows_set) {
-                if (rows > 2 * H) continue;
-                for (int tk = 0; tk < 4; ++tk) cand.push_back(TileChoice{px, rows, tk & 1, tk >> 1});
-            }
-        }
-        int next_copy = 0;
+        int next = 0;
         auto launch = [&](const TileChoice &t) -> bool {
-            const void *src = static_cast<const char *>(in) + next_copy * in_bytes;
-            next_copy = (next_copy + 1) % ncopy;
+            const void *src = static_cast<const char *>(in) + next * in_bytes;
+            void *dst = static_cast<char *>(out) + next * out_bytes;
+            uint8_t *msk = mask + next * npx;
+            next = (next + 1) % nset;
             return uniform_impl(ctx, src, B, H, W, W, (int64_t)H * W, &K, kind, grad, agg,
-                                out_type, out, W, 3LL * H * W, mask, W, (int64_t)H * W, st,
+                                out_type, dst, W, 3LL * H * W, msk, W, (int64_t)H * W, st,
                                 &t) == SNE_OK;
         };
-        int burst = 3;  // launches per timing, sized below to about 2 ms
-        auto time_one = [&](const TileChoice &t, float &ms) -> bool {
-            if (!launch(t)) return false;  // warm-up
-            hipEventRecord(e0, st);
-            for (int i = 0; i < burst; ++i)
-                if (!launch(t)) return false;
-            hipEventRecord(e1, st);
-            if (hipEventSynchronize(e1) != hipSuccess) return false;
-            hipEventElapsedTime(&ms, e0, e1);
-            ms /= burst;
-            return true;
-        };
-        {
-            float ms = 0.f;
-            const TileChoice t0 = default_tile(ctx, H, W, B, pxmax);
-            if (time_one(t0, ms) && ms > 0.f)
-                burst = (int)std::min(64.f, std::max(3.f, std::ceil(2.0f / ms)));
-        }
-        std::vector<std::pair<float, size_t>> first;
-        for (size_t i = 0; i < cand.size(); ++i) {
-            float ms;
-            if (time_one(cand[i], ms)) first.emplace_back(ms, i);
-        }
-        std::sort(first.begin(), first.end());
-        if (first.size() > 8) first.resize(8);
-        constexpr int kRounds = 7;
-        std::vector<std::vector<float>> rounds(first.size());
-        for (int r = 0; r < kRounds; ++r)
-            for (size_t j = 0; j < first.size(); ++j) {
-                float ms;
-                if (time_one(cand[first[j].second], ms)) rounds[j].push_back(ms);
-            }
-        float best_ms = 1e30f;
-        for (size_t j = 0; j < first.size(); ++j) {
-            std::vector<float> &v = rounds[j];
-            if (v.empty()) continue;
-            std::sort(v.begin(), v.end());
-            const float med = v[v.size() / 2];
-            if (med < best_ms) {
-                best_ms = med;
-                best = cand[first[j].second];
-            }
-        }
+        best = pick_fastest(tile_candidates(H, pxmax, true), default_tile(ctx, H, W, B, pxmax),
+                            launch, st, e0, e1);
         if (best.rows == 0) rc = SNE_ERR_HIP;
     }
     if (e0) hipEventDestroy(e0);
@@ -554,11 +601,41 @@ int sne_autotune(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int gr
     if (mask) hipFree(mask);
     if (rc != SNE_OK) return rc;
     ctx->cache[TileKey{H, W, batch_class(B), kind, grad, agg, out_type}] = best;
-    if (tile) {
-        tile->cols_per_lane = best.px;
-        tile->rows = best.rows;
-        tile->lanes = best.half ? 32 : 64;
+    report_tile(best, tile);
+    return SNE_OK;
+}
+
+int sne_autotune_batched(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int grad,
+                         int agg, int out_type, sne_tile *tile) {
+    if (!ctx || n < 1 || !frames || !valid_enum(kind, grad, agg, out_type)) return SNE_ERR_ARG;
+    int maxH = 0, maxW = 0, pxmax = 4;
+    const int rc0 = scan_batch(ctx, frames, n, kind, out_type, maxH, maxW, pxmax);
+    if (rc0 != SNE_OK) return rc0;
+    hipSetDevice(ctx->device);
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = SNE_OK;
+    if (hipStreamCreate(&st) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess)
+        rc = SNE_ERR_HIP;
+    TileChoice best{0, 0, 0, 0};
+    if (rc == SNE_OK) {
+        auto launch = [&](const TileChoice &t) -> bool {
+            return batched_impl(ctx, frames, n, kind, grad, agg, out_type, st, &t) == SNE_OK;
+        };
+        const Variant v{kind, grad, agg, out_type, 1};
+        best = pick_fastest(tile_candidates(maxH, pxmax, false),
+                            pick_tile(ctx, maxH, maxW, n, v, pxmax, true), launch, st, e0, e1);
+        if (best.rows == 0) rc = SNE_ERR_HIP;
+        // the slots' last batches ran on st: finish them before st goes away
+        if (hipStreamSynchronize(st) != hipSuccess) rc = SNE_ERR_HIP;
     }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (st) hipStreamDestroy(st);
+    if (rc != SNE_OK) return rc;
+    ctx->cache[TileKey{maxH, maxW, kUnevenClass, kind, grad, agg, out_type}] = best;
+    report_tile(best, tile);
     return SNE_OK;
 }
 
@@ -593,7 +670,7 @@ int sne_autotune_load(sne_ctx *ctx, const char *path) {
         if (got != 12 && got != 13) continue;
         if (ctx->arch != arch || ver != kVersion) continue;
         if (!valid_enum(kind, grad, agg, out) || !(px == 1 || px == 2 || px == 4) || rows < 1 ||
-            rows > 1024)
+            rows > 1024 || bc < 0 || bc > kUnevenClass)
             continue;
         ctx->cache[TileKey{H, W, bc, kind, grad, agg, out}] =
             TileChoice{px, rows, remap ? 1 : 0, half ? 1 : 0};

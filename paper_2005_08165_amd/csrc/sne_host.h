@@ -17,6 +17,10 @@ namespace sne {
 constexpr int kVersion = 10000;  // 1.0.0
 constexpr int kSlots = 4;        // in-flight uneven batches per context
 
+// Batch classes of the tile cache: 0 one frame, 1 up to 8, 2 more (uniform
+// batches), kUnevenClass shapes tuned on the persistent uneven-batch kernel.
+constexpr int kUnevenClass = 3;
+
 struct TileKey {
     int H, W, bclass, kind, grad, agg, out;
     bool operator<(const TileKey &o) const {
@@ -89,5 +93,8 @@ struct sne_ctx {
 };
 
 namespace sne {
-TileChoice pick_tile(const sne_ctx *ctx, int H, int W, int64_t B, const Variant &v, int pxmax);
+// Tile shape for a batch: forced shape, else the cache (for an uneven batch
+// first its own class), else the heuristic.
+TileChoice pick_tile(const sne_ctx *ctx, int H, int W, int64_t B, const Variant &v, int pxmax,
+                     bool uneven = false);
 }  // namespace sne

@@ -407,3 +407,19 @@ def uneven_sizes(n: int, seed: int = 3999,
     rng = np.random.default_rng(seed)
     idx = rng.integers(0, len(shapes), size=n)
     return [tuple(shapes[i]) for i in idx]
+
+
+def uneven_batch(n: int, seed: int = 3999, scenes_per_shape: int = 16, device="cpu"):
+    """The uneven-batch workload: n uint16 millimetre depth frames with shapes
+    from ``uneven_sizes(n, seed)``, ``scenes_per_shape`` distinct scenes per
+    shape reused across the batch.  Returns (shapes, Ks, k_index, frames):
+    Ks holds one intrinsics tuple per distinct shape (sorted), k_index the
+    row of Ks of each frame."""
+    shapes = uneven_sizes(n, seed=seed)
+    uniq = sorted(set(shapes))
+    cams = {sh: camera_for(*sh) for sh in uniq}
+    pool = {sh: [make_u16(seed + 1 + 97 * j + i, cams[sh], device=device).raw
+                 for j in range(scenes_per_shape)] for i, sh in enumerate(uniq)}
+    kidx = {sh: i for i, sh in enumerate(uniq)}
+    frames = [pool[sh][k % scenes_per_shape] for k, sh in enumerate(shapes)]
+    return shapes, [cams[sh].as_tuple() for sh in uniq], [kidx[sh] for sh in shapes], frames

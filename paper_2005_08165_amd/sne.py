@@ -132,6 +132,8 @@ _SIGS = {
     "sne_set_tile": ([_vp, ctypes.POINTER(Tile)], _int),
     "sne_get_tile": ([_vp, _i32, _i32, _i32, _int, _int, _int, _int, ctypes.POINTER(Tile)], _int),
     "sne_autotune": ([_vp, _i32, _i32, _i32, _int, _int, _int, _int, ctypes.POINTER(Tile)], _int),
+    "sne_autotune_batched": ([_vp, ctypes.POINTER(FrameDesc), _i32, _int, _int, _int, _int,
+                              ctypes.POINTER(Tile)], _int),
     "sne_autotune_save": ([_vp, ctypes.c_char_p], _int),
     "sne_autotune_load": ([_vp, ctypes.c_char_p], _int),
     "sne_server_create": ([ctypes.POINTER(_vp), _vp, ctypes.POINTER(ServerConfig)], _int),
@@ -255,6 +257,16 @@ class Context:
         check("sne_autotune", lib().sne_autotune(self._h, H, W, B, _enum(KIND, kind, "kind"),
                                                  _enum(GRAD, grad, "grad"), _enum(AGG, agg, "agg"),
                                                  _enum(OUT, out, "out"), ctypes.byref(t)))
+        return t.cols_per_lane, t.rows, t.lanes
+
+    def autotune_batched(self, descs, kind="depth_u16", grad="fd", agg="mean", out="f16"):
+        """sne_autotune_batched on a prepared descriptor array (its outputs
+        are written); returns (cols_per_lane, rows, lanes)."""
+        t = Tile()
+        check("sne_autotune_batched",
+              lib().sne_autotune_batched(self._h, descs, len(descs), _enum(KIND, kind, "kind"),
+                                         _enum(GRAD, grad, "grad"), _enum(AGG, agg, "agg"),
+                                         _enum(OUT, out, "out"), ctypes.byref(t)))
         return t.cols_per_lane, t.rows, t.lanes
 
     def autotune_save(self, path: str):

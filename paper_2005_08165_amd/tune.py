@@ -2,7 +2,8 @@
 
     python -m paper_2005_08165_amd.tune [--out FILE]
 
-Runs the library's autotuner (sne_autotune) on each standard workload below
+Runs the library's autotuner on each standard workload below (sne_autotune
+for uniform batches, sne_autotune_batched for the uneven persistent batch)
 and writes the resulting table (sne_autotune_save format).  A Context loads
 the shipped table, ``tuning.txt`` beside this file, when it is created; lines
 for other GPU architectures or library versions are ignored.
@@ -29,7 +30,17 @@ WORKLOADS = [
 ]
 
 
+# uneven persistent batches, tuned on the batch itself: (frames, input kind,
+# gradient filter, aggregation, output type)
+UNEVEN = [
+    (1024, "depth_u16", "fd", "mean", "f16"),
+    (1024, "depth_u16", "fd", "median", "f16"),
+]
+
+
 def main(argv=None):
+    import torch
+    from . import scenes
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=TABLE)
     args = ap.parse_args(argv)
@@ -38,6 +49,15 @@ def main(argv=None):
         t = ctx.autotune(H, W, B, kind, grad, agg, out)
         print("%dx%d B=%d %s %s-%s %s -> cols_per_lane %d rows %d lanes %d"
               % (H, W, B, kind, grad, agg, out, *t), flush=True)
+    for n, kind, grad, agg, out in UNEVEN:
+        shapes, Ks, ki, frames = scenes.uneven_batch(n, device="cuda")
+        ctx.set_intrinsics_table(Ks)
+        descs, nrm, msk = ctx.prepare_batched(frames, ki, kind, out)
+        t = ctx.autotune_batched(descs, kind, grad, agg, out)
+        print("uneven %d frames %s %s-%s %s -> cols_per_lane %d rows %d lanes %d"
+              % (n, kind, grad, agg, out, *t), flush=True)
+        del frames, nrm, msk
+        torch.cuda.empty_cache()
     ctx.autotune_save(args.out)
     print(args.out)
     return 0

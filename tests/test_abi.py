@@ -113,7 +113,7 @@ def test_shipped_tuning_table_is_well_formed():
         assert len(f) == 13, line
         arch, ver, H, W, bc, kind, grad, agg, out, px, rows, remap, half = (
             [f[0]] + [int(x) for x in f[1:]])
-        assert ver == sne.version() and H >= 1 and W >= 1 and bc in (0, 1, 2)
+        assert ver == sne.version() and H >= 1 and W >= 1 and bc in (0, 1, 2, 3)
         assert kind in sne.KIND.values() and grad in sne.GRAD.values()
         assert agg in sne.AGG.values() and out in (0, 1)
         assert px in (1, 2, 4) and 1 <= rows <= 1024 and remap in (0, 1) and half in (0, 1)

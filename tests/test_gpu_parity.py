@@ -389,6 +389,41 @@ def test_autotune_and_tuning_table():
         assert torch.equal(n, outs[0][0]) and torch.equal(m, outs[0][1])
 
 
+def test_autotune_batched():
+    """The batched autotuner times shapes on the caller's uneven batch, keeps
+    a valid shape for uneven batches (saved as batch class 3), and the batch
+    run with it equals the same batch run with the heuristic shape and with
+    single calls, bitwise; the uniform-batch choice is left alone."""
+    import os, tempfile
+    shapes = [(60, 80), (120, 160), (37, 211), (120, 160), (60, 80), (90, 130)]
+    cams = [S.camera_for(*sh) for sh in shapes]
+    frames = [S.make_u16(1200 + i, cams[i], device="cuda").raw for i in range(len(shapes))]
+    ctx = sne.Context(0, tuning=False)
+    ctx.set_intrinsics_table([c.as_tuple() for c in cams])
+    before = ctx.get_tile(120, 211, len(shapes), "depth_u16", "fd", "median", "f16")
+    descs, nt, mt = ctx.prepare_batched(frames, list(range(len(shapes))), "depth_u16", "f16")
+    t = ctx.autotune_batched(descs, "depth_u16", "fd", "median", "f16")
+    assert t[0] in (1, 2, 4) and 1 <= t[1] <= 1024 and t[2] in (32, 64)
+    assert ctx.get_tile(120, 211, len(shapes), "depth_u16", "fd", "median", "f16") == before
+    ctx.run_batched(descs, "depth_u16", "fd", "median", "f16")
+    plain = sne.Context(0, tuning=False)
+    plain.set_intrinsics_table([c.as_tuple() for c in cams])
+    nh, mh = plain.estimate_batched(frames, list(range(len(shapes))), "depth_u16", "fd", "median",
+                                    "f16")
+    torch.cuda.synchronize()
+    for i, f in enumerate(frames):
+        n1, m1 = sne.estimate(f, cams[i].as_tuple(), "depth_u16", "fd", "median", "f16", ctx=plain)
+        torch.cuda.synchronize()
+        assert torch.equal(nt[i], nh[i]) and torch.equal(mt[i], mh[i]), i
+        assert torch.equal(nt[i], n1) and torch.equal(mt[i], m1), i
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "cache.txt")
+        ctx.autotune_save(path)
+        rows = [l.split() for l in open(path) if not l.startswith("#")]
+    assert [int(x) for x in rows[0][2:9]] == [120, 211, 3, 1, 0, 1, 1]
+    assert (int(rows[0][9]), int(rows[0][10]), 32 if int(rows[0][12]) else 64) == t
+
+
 def test_determinism():
     fr = S.make_cluttered(1004)
     raw = fr.raw.cuda()
