@@ -122,7 +122,7 @@ def copy_calibration(torch, nbytes=1 << 30, reps=10):
             "us_per_copy": round(ev / reps * 1e6, 1)}
 
 
-def uneven_batch(torch, S, sne, agg, n_frames=1024, reps=5, autotune=False):
+def uneven_batch(torch, S, sne, agg, n_frames=1024, reps=20, warmup=10, autotune=False):
     """One persistent launch over n_frames frames of sizes drawn uniformly
     from {240x320, 480x640, 720x1280, 1080x1920}: uint16 millimetre depth in,
     FP16 normals + mask out (9 B/px), FD gradients, tile shape from the
@@ -137,7 +137,7 @@ def uneven_batch(torch, S, sne, agg, n_frames=1024, reps=5, autotune=False):
     if autotune:
         ctx.autotune_batched(descs, "depth_u16", "fd", agg, "f16")
     wall, ev = time_launches(torch, lambda i: ctx.run_batched(descs, "depth_u16", "fd", agg, "f16"),
-                             2, reps)
+                             warmup, reps)
     px = sum(h * w for h, w in shapes)
     return {"frames": n_frames, "mpix": round(px / 1e6, 1), "agg": agg,
             "ms_per_launch": round(ev / reps * 1e3, 3),
@@ -247,8 +247,12 @@ def cpu_baseline(host_batch, K, grad, agg, min_s=10.0, budget_s=20.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    # In a kernel trace of a sustained run the launches take ~78 us at first,
+    # ~90 us from about the 20th (the device's power management reacting to
+    # the load, presumably) and settle at ~76 us from about the 300th on:
+    # the defaults time the steady state (3000 launches, 0.23 s of GPU time).
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--grad", default="sobel")
     ap.add_argument("--agg", default="median")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -91,7 +91,7 @@ typedef struct {
 typedef struct sne_ctx sne_ctx;
 
 /* Create a context bound to HIP device `device`.  The context owns small
- * device tables (descriptors, intrinsics, a tile counter) and the tile-shape
+ * device tables (descriptors, intrinsics, tile queues) and the tile-shape
  * cache of the autotuner.  *out is set to NULL on failure. */
 int sne_ctx_create(sne_ctx **out, int device);
 
@@ -140,8 +140,8 @@ typedef struct {
 int sne_set_intrinsics_table(sne_ctx *ctx, const sne_intrinsics *K, int32_t n);
 
 /* n frames of any sizes (host array of descriptors) in ONE persistent launch:
- * a grid sized to the GPU pulls tiles from a device counter until every tile
- * of every frame is done.  All frames share kind, grad, agg and out type.
+ * a grid sized to the GPU pulls tiles from eight device queues (one per XCD,
+ * contiguous tile ranges) until every tile of every frame is done.  All frames share kind, grad, agg and out type.
  * Bitwise identical, frame by frame, to sne_estimate with the same K.
  * n = 0 launches nothing (frames may then be NULL).
  * The descriptor table is staged through pinned memory owned by the context,
