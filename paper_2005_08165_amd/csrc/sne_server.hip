@@ -52,7 +52,7 @@ public:
     uint8_t *arena = nullptr;
     std::vector<SlotRes> slots;
     size_t cap = 0;
-    int rows = 16;
+    TileChoice tile{4, 16, 0, 0};  // shape of the persistent kernel's tiles
 
     int init(sne_ctx *c, const sne_server_config &conf, uint8_t *arena_base) {
         ctx = c;
@@ -90,7 +90,7 @@ public:
         BatchArgs a;
         a.table = s.d_stage;
         a.ktable = reinterpret_cast<const float4 *>(ctx->d_K);
-        a.rows = rows;
+        a.rows = tile.rows;
         a.chunk = 1;
         grad_weights(cfg.grad, a.wa, a.wb);
         return a;
@@ -104,20 +104,20 @@ public:
     // The steps of one batch, enqueued on the slot's stream: the table copy
     // (`bytes` of it; a captured graph copies the whole capacity) and the
     // persistent kernel.
-    hipError_t enqueue(SlotRes &s, int px, size_t bytes) {
+    hipError_t enqueue(SlotRes &s, int kpx, size_t bytes) {
         hipError_t e = hipMemcpyAsync(s.d_stage, s.h_stage, bytes, hipMemcpyHostToDevice,
                                       s.stream);
         if (e != hipSuccess) return e;
-        Variant v{cfg.kind, cfg.grad, cfg.agg, cfg.out_type, px};
+        Variant v{cfg.kind, cfg.grad, cfg.agg, cfg.out_type, kpx};
         return launch_batch(v, args(s), grid(), s.stream);
     }
 
-    int build_graph(SlotRes &s, int px) {
+    int build_graph(SlotRes &s, const TileChoice &t) {
         hipGraph_t g = nullptr;
         hipGraphExec_t ex = nullptr;
         if (hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return SNE_ERR_HIP;
-        const hipError_t e = enqueue(s, px, s.bytes);
+        const hipError_t e = enqueue(s, kernel_px(t), s.bytes);
         const hipError_t e2 = hipStreamEndCapture(s.stream, &g);
         if (e != hipSuccess || e2 != hipSuccess || !g) {
             if (g) (void)hipGraphDestroy(g);
@@ -126,7 +126,7 @@ public:
         const hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (e3 != hipSuccess) return SNE_ERR_HIP;
-        s.graph[px_index(px)] = ex;
+        s.graph[px_index(t.px)] = ex;
         return SNE_OK;
     }
 
@@ -135,13 +135,15 @@ public:
         const int64_t nb = (int64_t)b.reqs.size();
         const BatchTable bt = batch_table(s.h_stage, nb);
         const size_t oe = out_elem(cfg.out_type);
-        int px = 4;
+        int px = tile.px;
         for (auto *q : b.reqs) {
             uint8_t *out = arena + q->out_offset;
             uint8_t *mask = out + 3 * (size_t)q->H * q->W * oe;
             px = std::min(px, max_px(q->in, out, mask, q->W, q->in_pitch, q->W, q->W, 0, 0, 0,
                                      (int64_t)q->H * q->W, cfg.kind, cfg.out_type));
         }
+        TileChoice t = tile;
+        t.px = px;
         int64_t tiles = 0;
         for (int64_t i = 0; i < nb; ++i) {
             auto *q = b.reqs[i];
@@ -151,8 +153,8 @@ public:
             bt.frames[i] = make_desc(q->in, out, mask, q->H, q->W, q->in_pitch, q->W, q->W,
                                      unused);
             bt.frames[i].k_index = q->stream;
-            const int nst = (q->W + 64 * px - 1) / (64 * px);
-            const int nbands = (q->H + rows - 1) / rows;
+            const int nst = tile_nstrips(q->W, t);
+            const int nbands = tile_nbands(q->H, t);
             bt.tile_start[i] = (int32_t)tiles;
             bt.nstrips[i] = nst;
             tiles += (int64_t)nst * nbands;
@@ -171,12 +173,12 @@ public:
                 s.graph_ktable = ctx->d_K;
             }
             if (!s.graph[px_index(px)]) {
-                const int rc = build_graph(s, px);
+                const int rc = build_graph(s, t);
                 if (rc != SNE_OK) return rc;
             }
             e = hipGraphLaunch(s.graph[px_index(px)], s.stream);
         } else {
-            e = enqueue(s, px, batch_table_bytes(nb));
+            e = enqueue(s, kernel_px(t), batch_table_bytes(nb));
         }
         if (e != hipSuccess || hipEventRecord(s.done, s.stream) != hipSuccess) return SNE_ERR_HIP;
         s.launched = true;
@@ -291,8 +293,9 @@ int sne_server_create(sne_server **out, sne_ctx *ctx, const sne_server_config *c
         delete s;
         return SNE_ERR_HIP;
     }
+    // the shape tuned for uneven batches of frames up to 1080x1920, if any
     Variant v{cfg->kind, cfg->grad, cfg->agg, cfg->out_type, 4};
-    s->ex.rows = pick_tile(ctx, 1080, 1920, cfg->max_batch_frames, v, 4).rows;
+    s->ex.tile = pick_tile(ctx, 1080, 1920, cfg->max_batch_frames, v, 4, true);
     sched::Config sc;
     sc.max_inflight = cfg->max_inflight;
     sc.max_batch_frames = cfg->max_batch_frames;
