@@ -419,6 +419,9 @@ __device__ __forceinline__ float median8(const float (&Nj)[8], const float (&rj)
     return median_pair(t, pad < 0.f);  // odd number left out -> position 3
 }
 
+// Mean of the kept candidates.  Both paths add in the same tree order and
+// 1/8 is exact, so a pixel with nothing left out gets the same bits whichever
+// path its wavefront takes.
 template <int KIND>
 __device__ __forceinline__ float mean8(const float (&Nj)[8], const float (&rj)[8],
                                        const float (&zj)[8], float zc, bool general, bool &none) {
@@ -429,16 +432,16 @@ __device__ __forceinline__ float mean8(const float (&Nj)[8], const float (&rj)[8
         const float s = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
         return s * 0.125f;
     }
-    float sum = 0.f;
     int m = 0;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const bool drop = zj[j] == zc;
-        sum += drop ? 0.f : t[j];
+        t[j] = drop ? 0.f : t[j];
         m += drop ? 0 : 1;
     }
     none = (m == 0);
-    return sum * rcp((float)m);
+    const float s = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
+    return s * (m == 8 ? 0.125f : rcp((float)m));
 }
 
 // Outputs are written once and not read back by this kernel: nontemporal

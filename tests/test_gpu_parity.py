@@ -424,6 +424,33 @@ def test_autotune_batched():
     assert (int(rows[0][9]), int(rows[0][10]), 32 if int(rows[0][12]) else 64) == t
 
 
+@pytest.mark.parametrize("grad,agg", [("fd", "mean"), ("sobel", "mean"), ("fd", "median"),
+                                      ("scharr", "median")])
+def test_aggregation_path_does_not_change_other_pixels(grad, agg):
+    """A wavefront takes the general aggregation path when any of its valid
+    pixels has a left-out neighbour.  Planting such a tie changes the path of
+    the pixels around it but must not change their bits: every pixel whose
+    window does not see the planted value is bitwise identical with and
+    without it."""
+    fr = S.make_cluttered(1300)
+    a = fr.raw.clone()
+    b = a.clone()
+    spots = [(37, 100), (240, 333), (241, 334), (400, 17), (111, 600)]
+    for v, u in spots:
+        b[v, u] = b[v, u + 1]  # a tie between two valid-or-not samples
+    na, ma = sne.estimate(a.cuda(), fr.cam.as_tuple(), "depth_f32", grad, agg)
+    nb, mb = sne.estimate(b.cuda(), fr.cam.as_tuple(), "depth_f32", grad, agg)
+    torch.cuda.synchronize()
+    keep = torch.ones(a.shape, dtype=torch.bool)
+    for v, u in spots:
+        keep[max(v - 2, 0):v + 3, max(u - 2, 0):u + 4] = False
+    na, nb = na.cpu(), nb.cpu()
+    assert torch.equal(ma.cpu()[keep], mb.cpu()[keep])
+    for c in range(3):
+        diff = (na[c].view(torch.int32) != nb[c].view(torch.int32)) & keep
+        assert not diff.any(), (c, diff.nonzero()[:5].tolist())
+
+
 def test_determinism():
     fr = S.make_cluttered(1004)
     raw = fr.raw.cuda()
