@@ -249,7 +249,11 @@ typedef struct {
 } sne_server_stats;
 
 /* Create a server on ctx (which must outlive it).  The frames' intrinsics are
- * read from ctx's table (sne_set_intrinsics_table) when each batch runs. */
+ * read from ctx's table (sne_set_intrinsics_table) when each batch runs.  The
+ * batches use the tile shape ctx holds for uneven batches of frames up to
+ * 1080x1920 of this variant (sne_autotune_batched, or the loaded table),
+ * else the one for uniform batches, else the built-in heuristic; it is fixed
+ * when the server is created. */
 int sne_server_create(sne_server **out, sne_ctx *ctx, const sne_server_config *cfg);
 /* Thread-safe.  SNE_ERR_BUDGET: the frame's outputs exceed the whole arena;
  * SNE_ERR_FULL: queue_capacity requests are already waiting (retry). */
