@@ -7,7 +7,8 @@ its Python binding) never loads it, and it shares no code with them.
 ``sne_oracle.c`` holds the arithmetic (see its header for the definition it
 follows, Sec. III of the paper); this module builds it with gcc, loads it with
 ctypes and marshals numpy arrays.  ``exact.py`` is an independent brute-force
-evaluation in rational arithmetic for tiny integer images.
+evaluation in rational arithmetic for tiny integer images.  ``accuracy``
+evaluates the paper's accuracy metrics e_A and e_P (eq. ea_ep) in numpy.
 """
 from __future__ import annotations
 
@@ -143,3 +144,26 @@ def angular_error_deg(a: np.ndarray, b: np.ndarray, axis: int = 0) -> np.ndarray
     b = np.asarray(b, np.float64)
     cr = np.cross(a, b, axisa=axis, axisb=axis, axisc=axis)
     return np.degrees(np.arctan2(np.linalg.norm(cr, axis=axis), np.sum(a * b, axis=axis)))
+
+
+def accuracy(est: np.ndarray, gt: np.ndarray, mask: Optional[np.ndarray] = None,
+             phis: Sequence[float] = (11.25, 22.5, 30.0)):
+    """Accuracy metrics of eq. ea_ep (Sec. IV-A) in FP64, written as the
+    paper defines them: psi_k = arccos(<n_k, g_k> / (|n_k| |g_k|)) in degrees
+    over the m pixels evaluated (those with mask != 0; all if mask is None),
+    e_A = mean psi_k, e_P(phi) = fraction of pixels with psi_k <= phi.
+    est, gt: [..., 3, H, W] (any leading frame axes); mask: [..., H, W].
+    Returns (e_A, [e_P(phi) for phi in phis], m); e_A = e_P = 0 when m = 0."""
+    n = np.asarray(est, np.float64)
+    g = np.asarray(gt, np.float64)
+    n = np.moveaxis(n, -3, -1).reshape(-1, 3)
+    g = np.moveaxis(g, -3, -1).reshape(-1, 3)
+    if mask is not None:
+        keep = np.asarray(mask).reshape(-1) != 0
+        n, g = n[keep], g[keep]
+    m = n.shape[0]
+    if m == 0:
+        return 0.0, [0.0 for _ in phis], 0
+    c = np.sum(n * g, axis=1) / (np.linalg.norm(n, axis=1) * np.linalg.norm(g, axis=1))
+    psi = np.degrees(np.arccos(np.clip(c, -1.0, 1.0)))
+    return float(psi.mean()), [float(np.mean(psi <= phi)) for phi in phis], m

@@ -407,3 +407,63 @@ def test_argument_errors():
         oracle.estimate(z, "depth_f32", (0.0, 1.0, 2.0, 2.0))
     with pytest.raises(TypeError):
         oracle.estimate(z.astype(np.float64), "depth_f32", (1, 1, 2, 2))
+
+
+def _rotated_pairs(rng, n, theta_deg):
+    """Unit ground-truth vectors g and vectors n at the given angles from
+    them (then scaled by arbitrary positive factors), as [3, n] arrays."""
+    g = rng.normal(size=(n, 3))
+    g /= np.linalg.norm(g, axis=1, keepdims=True)
+    a = rng.normal(size=(n, 3))
+    u = np.cross(g, a)
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    t = np.radians(theta_deg)[:, None]
+    v = np.cos(t) * g + np.sin(t) * u
+    v *= rng.uniform(0.1, 10.0, size=(n, 1))
+    return v.T.copy(), g.T.copy()
+
+
+def test_accuracy_metrics_closed_form():
+    """eq. ea_ep: with n_k built at a known angle theta_k from g_k, psi_k =
+    theta_k, so e_A is the mean angle and e_P(phi) the share of angles up to
+    phi, whatever the lengths of n_k."""
+    rng = np.random.default_rng(11)
+    theta = rng.uniform(0.0, 180.0, size=4000)
+    phis = (11.25, 22.5, 30.0, 90.0)
+    for p in phis:  # keep clear of the thresholds
+        theta[np.abs(theta - p) < 1e-6] += 2e-6
+    v, g = _rotated_pairs(rng, theta.size, theta)
+    eA, eP, m = oracle.accuracy(v.reshape(3, 40, 100), g.reshape(3, 40, 100), phis=phis)
+    assert m == theta.size
+    assert abs(eA - theta.mean()) < 1e-9
+    assert eP == [float(np.mean(theta <= p)) for p in phis]
+
+
+def test_accuracy_metrics_special_cases_and_mask():
+    g = np.zeros((3, 1, 4))
+    g[2] = -1.0
+    n = np.array([[0, 0, 1, 0], [0, 0, 0, 0], [-2, -1, 0, 1]], float)[:, None, :]
+    n[0, 0, 0] = 0.0
+    # same direction (scaled), same, orthogonal, opposite
+    eA, eP, m = oracle.accuracy(n, g, phis=(0.0, 90.0, 180.0))
+    assert m == 4 and abs(eA - (0 + 0 + 90 + 180) / 4) < 1e-12
+    assert eP == [0.5, 0.75, 1.0]
+    mask = np.array([[1, 0, 0, 1]], np.uint8)
+    eA, eP, m = oracle.accuracy(n, g, mask, phis=(90.0,))
+    assert m == 2 and abs(eA - 90.0) < 1e-12 and eP == [0.5]
+    assert oracle.accuracy(n, g, np.zeros((1, 4), np.uint8)) == (0.0, [0.0, 0.0, 0.0], 0)
+
+
+def test_accuracy_metrics_agree_with_the_atan2_angle_and_frame_axes():
+    """The arccos form of the paper and the atan2 form agree away from 0 and
+    180 degrees; a leading frame axis is flattened like the pixels."""
+    rng = np.random.default_rng(12)
+    theta = rng.uniform(1.0, 179.0, size=2 * 3 * 50)
+    v, g = _rotated_pairs(rng, theta.size, theta)
+    v = v.reshape(3, 2, 3, 50).transpose(1, 0, 2, 3)
+    g = g.reshape(3, 2, 3, 50).transpose(1, 0, 2, 3)
+    mask = rng.integers(0, 2, size=(2, 3, 50)).astype(np.uint8)
+    eA, eP, m = oracle.accuracy(v, g, mask, phis=(45.0,))
+    psi = np.stack([oracle.angular_error_deg(v[b], g[b]) for b in range(2)])[mask != 0]
+    assert m == int(mask.sum())
+    assert abs(eA - psi.mean()) < 1e-9 and eP == [float(np.mean(psi <= 45.0))]
