@@ -148,6 +148,46 @@ def uneven_batch(torch, S, sne, agg, n_frames=1024, reps=20, warmup=10, autotune
             "note": "event time per call: table copy (it also resets the tile queues) + kernel"}
 
 
+def accuracy_eval(torch, S, sne, reps=100, phis=(11.25, 22.5, 30.0)):
+    """On-device accuracy metrics (e_A, e_P of the paper's evaluation) of the
+    batched estimate against the analytic normals of its scenes: 64 frames of
+    the benchmark's scene recipe with ground truth, Sobel-median; the timed
+    pass reads 12 B of normals + 12 B of ground truth + 1 B of mask per pixel."""
+    import ctypes
+    B, H, W = 64, 480, 640
+    cam = S.Camera(H, W, *S.INDOOR_K)
+    raws, gts = [], []
+    for i in range(B):
+        fr = S.make_cluttered(1000 + i, cam, device="cuda", need_gt=True)
+        raws.append(fr.raw)
+        gts.append(fr.gt.float())
+    raw = torch.stack(raws)
+    gt = torch.stack(gts).contiguous()
+    del raws, gts
+    ctx = sne.Context(0)
+    nrm, msk = sne.estimate_uniform(raw, cam.as_tuple(), "depth_f32", "sobel", "median", ctx=ctx)
+    eA, eP, m = ctx.accuracy(nrm, gt, msk, phis)
+    res = torch.empty(2 + len(phis), dtype=torch.float64, device="cuda")
+    ph = (ctypes.c_float * len(phis))(*phis)
+    st = torch.cuda.current_stream().cuda_stream
+    L = sne.lib()
+
+    def call(i):
+        rc = L.sne_accuracy(ctx.handle, nrm.data_ptr(), 0, gt.data_ptr(), msk.data_ptr(), B,
+                            H * W, ph, len(phis), res.data_ptr(), st)
+        if rc != 0:
+            raise RuntimeError("sne_accuracy: %s" % sne.status_string(rc))
+
+    wall, ev = time_launches(torch, call, 10, reps)
+    px = B * H * W
+    return {"frames": B, "grad": "sobel", "agg": "median", "e_A_deg": round(eA, 4),
+            "e_P": {str(p): round(v, 4) for p, v in zip(phis, eP)}, "pixels_evaluated": m,
+            "us_per_call": round(ev / reps * 1e6, 2),
+            "gpx_per_s": round(px * reps / ev / 1e9, 1),
+            "achieved_GBs": round(px * 25 * reps / ev / 1e9, 1),
+            "frac_of_peak": round(px * 25 * reps / ev / 1e9 / PEAK_HBM_GBS, 4)}
+
+
 def serving(torch, S, sne, duration=2.0, slo_p99_ms=2.0, plain_run=True,
             plan=(("mean", (20000, 60000, 100000, 120000, 140000, 160000)),
                   ("median", (20000, 60000, 100000, 120000, 140000)))):
@@ -259,6 +299,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--serving-rate", type=float, default=0.0,
                     help="run the serving loop at this one offered rate (FD-mean) only")
     ap.add_argument("--autotune", action="store_true",
@@ -348,6 +389,9 @@ def main():
         log("uneven persistent batch")
         res["uneven_batch"] = [uneven_batch(torch, S, sne, "mean", autotune=args.autotune),
                                uneven_batch(torch, S, sne, "median", autotune=args.autotune)]
+    if not args.no_accuracy:
+        log("accuracy metrics on the device")
+        res["accuracy_eval"] = accuracy_eval(torch, S, sne)
     if not args.no_serving:
         log("serving loop")
         if args.serving_rate > 0:

@@ -196,6 +196,22 @@ int sne_autotune_batched(sne_ctx *ctx, const sne_frame *frames, int32_t n, int k
 int sne_autotune_save(const sne_ctx *ctx, const char *path);
 int sne_autotune_load(sne_ctx *ctx, const char *path);
 
+/* Accuracy of estimated normals against ground truth, the metrics of
+ * eq. ea_ep (Sec. IV-A): psi_k = angle between estimate and ground truth at
+ * pixel k (degrees), over the pixels with mask != 0 (all if mask is NULL);
+ * e_A = mean psi_k, e_P(phi_j) = share of pixels with psi_k <= phi_j.
+ * normals: B frames of [3][frame_px] (out_type FP32 or FP16, contiguous);
+ * gt: B frames of [3][frame_px] FP32; mask: B frames of [frame_px] u8 or NULL.
+ * phis_deg: host array of nphi <= 8 thresholds in degrees.
+ * result: DEVICE array of 2 + nphi doubles, written asynchronously on `stream`:
+ * {e_A, m, e_P(phi_0), ...}; all 0 when m = 0.  The context's scratch table
+ * (allocated by the first call) is shared by all calls on ctx; a call on
+ * another stream waits for the previous call.  SNE_ERR_ARG on a NULL ctx or
+ * result, nphi outside 0..8, a bad out_type, or NULL data with B*frame_px > 0. */
+int sne_accuracy(sne_ctx *ctx, const void *normals, int out_type, const float *gt,
+                 const uint8_t *mask, int32_t B, int64_t frame_px, const float *phis_deg,
+                 int32_t nphi, double *result, void *stream);
+
 /* ------------------------------------------------------------------------
  * Serving loop.  A server owns an output arena of `hbm_budget_bytes` device
  * memory and a scheduler thread.  Submitted requests (one device-resident

@@ -42,6 +42,7 @@ def _units():
                       os.path.join(OBJ, "sne_kernels_k%d.o" % kind), ["-DSNE_KIND=%d" % kind]))
     units.append((os.path.join(CSRC, "sne_api.hip"), os.path.join(OBJ, "sne_api.o"), []))
     units.append((os.path.join(CSRC, "sne_server.hip"), os.path.join(OBJ, "sne_server.o"), []))
+    units.append((os.path.join(CSRC, "sne_eval.hip"), os.path.join(OBJ, "sne_eval.o"), []))
     units.append((os.path.join(CSRC, "sne_sched.cpp"), os.path.join(OBJ, "sne_sched.o"), []))
     return units
 

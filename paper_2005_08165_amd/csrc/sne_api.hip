@@ -195,14 +195,14 @@ int uniform_impl(sne_ctx *ctx, const void *in, int32_t B, int32_t H, int32_t W, 
     a.xcd_remap = t.remap;
     grad_weights(grad, a.wa, a.wb);
     const int grid = (int)((ntiles + kWavesPerBlock - 1) / kWavesPerBlock);
-    if (ctx) hipSetDevice(ctx->device);
+    if (ctx && hipSetDevice(ctx->device) != hipSuccess) return SNE_ERR_HIP;
     hipError_t e = launch_uniform(v, a, grid, (hipStream_t)stream);
     return e == hipSuccess ? SNE_OK : SNE_ERR_HIP;
 }
 
 void free_slot(Slot &s) {
-    if (s.d_table) hipFree(s.d_table);
-    if (s.h_stage) hipHostFree(s.h_stage);
+    if (s.d_table) (void)hipFree(s.d_table);
+    if (s.h_stage) (void)hipHostFree(s.h_stage);
     s = Slot{};
 }
 
@@ -210,7 +210,7 @@ int ensure_slot(Slot &s, size_t n) {
     if (!s.done && hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
         return SNE_ERR_HIP;
     if (n <= s.cap) return SNE_OK;
-    if (s.used) hipEventSynchronize(s.done);
+    if (s.used) (void)hipEventSynchronize(s.done);
     hipEvent_t ev = s.done;
     s.done = nullptr;
     free_slot(s);
@@ -267,7 +267,7 @@ int batched_impl(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int
     v.px = kernel_px(t);
     Slot &s = ctx->slots[ctx->next_slot];
     ctx->next_slot = (ctx->next_slot + 1) % kSlots;
-    hipSetDevice(ctx->device);
+    if (hipSetDevice(ctx->device) != hipSuccess) return SNE_ERR_HIP;
     int rc = ensure_slot(s, (size_t)n);
     if (rc != SNE_OK) return rc;
     if (s.used && hipEventSynchronize(s.done) != hipSuccess) return SNE_ERR_HIP;
@@ -361,12 +361,12 @@ TileChoice pick_fastest(const std::vector<TileChoice> &cand, const TileChoice &p
     int burst = 3;
     auto time_one = [&](const TileChoice &t, float &ms) -> bool {
         if (!launch(t)) return false;  // warm-up
-        hipEventRecord(e0, st);
+        if (hipEventRecord(e0, st) != hipSuccess) return false;
         for (int i = 0; i < burst; ++i)
             if (!launch(t)) return false;
-        hipEventRecord(e1, st);
+        if (hipEventRecord(e1, st) != hipSuccess) return false;
         if (hipEventSynchronize(e1) != hipSuccess) return false;
-        hipEventElapsedTime(&ms, e0, e1);
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return false;
         ms /= burst;
         return true;
     };
@@ -456,14 +456,19 @@ int sne_ctx_create(sne_ctx **out, int device) {
 int sne_ctx_destroy(sne_ctx *ctx) {
     if (!ctx) return SNE_OK;
     if (ctx->n_servers.load() > 0) return SNE_ERR_STATE;
-    hipSetDevice(ctx->device);
+    (void)hipSetDevice(ctx->device);  // release what can be released regardless
     for (auto &s : ctx->slots) {
-        if (s.used && s.done) hipEventSynchronize(s.done);
+        if (s.used && s.done) (void)hipEventSynchronize(s.done);
         hipEvent_t ev = s.done;
         free_slot(s);
-        if (ev) hipEventDestroy(ev);
+        if (ev) (void)hipEventDestroy(ev);
     }
-    if (ctx->d_K) hipFree(ctx->d_K);
+    if (ctx->d_K) (void)hipFree(ctx->d_K);
+    if (ctx->eval_done) {
+        (void)hipEventSynchronize(ctx->eval_done);
+        (void)hipEventDestroy(ctx->eval_done);
+    }
+    if (ctx->d_eval) (void)hipFree(ctx->d_eval);
     delete ctx;
     return SNE_OK;
 }
@@ -491,12 +496,12 @@ int sne_set_intrinsics_table(sne_ctx *ctx, const sne_intrinsics *K, int32_t n) {
     for (int32_t i = 0; i < n; ++i)
         if (!valid_K(&K[i], SNE_DEPTH_F32)) return SNE_ERR_ARG;
     if (ctx->n_servers.load() > 0) return SNE_ERR_STATE;
-    hipSetDevice(ctx->device);
+    if (hipSetDevice(ctx->device) != hipSuccess) return SNE_ERR_HIP;
     // wait for batches that may still read the old table
     for (auto &s : ctx->slots)
-        if (s.used && s.done) hipEventSynchronize(s.done);
+        if (s.used && s.done && hipEventSynchronize(s.done) != hipSuccess) return SNE_ERR_HIP;
     if (n > ctx->nK) {
-        if (ctx->d_K) hipFree(ctx->d_K);
+        if (ctx->d_K) (void)hipFree(ctx->d_K);
         ctx->d_K = nullptr;
         ctx->nK = 0;
         if (hipMalloc(&ctx->d_K, n * sizeof(sne_intrinsics)) != hipSuccess) return SNE_ERR_HIP;
@@ -543,7 +548,7 @@ int sne_autotune(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int gr
                  int out_type, sne_tile *tile) {
     if (!ctx || H < 1 || W < 1 || B < 1 || !valid_enum(kind, grad, agg, out_type))
         return SNE_ERR_ARG;
-    hipSetDevice(ctx->device);
+    if (hipSetDevice(ctx->device) != hipSuccess) return SNE_ERR_HIP;
     const int64_t npx = (int64_t)B * H * W;
     // Inputs and outputs form a ring of sets that together exceed the
     // last-level cache (256 MB) several times, so a timed launch reads and
@@ -593,12 +598,12 @@ int sne_autotune(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int gr
                             launch, st, e0, e1);
         if (best.rows == 0) rc = SNE_ERR_HIP;
     }
-    if (e0) hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
-    if (st) hipStreamDestroy(st);
-    if (in) hipFree(in);
-    if (out) hipFree(out);
-    if (mask) hipFree(mask);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+    if (in) (void)hipFree(in);
+    if (out) (void)hipFree(out);
+    if (mask) (void)hipFree(mask);
     if (rc != SNE_OK) return rc;
     ctx->cache[TileKey{H, W, batch_class(B), kind, grad, agg, out_type}] = best;
     report_tile(best, tile);
@@ -611,7 +616,7 @@ int sne_autotune_batched(sne_ctx *ctx, const sne_frame *frames, int32_t n, int k
     int maxH = 0, maxW = 0, pxmax = 4;
     const int rc0 = scan_batch(ctx, frames, n, kind, out_type, maxH, maxW, pxmax);
     if (rc0 != SNE_OK) return rc0;
-    hipSetDevice(ctx->device);
+    if (hipSetDevice(ctx->device) != hipSuccess) return SNE_ERR_HIP;
     hipStream_t st = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = SNE_OK;
@@ -630,9 +635,9 @@ int sne_autotune_batched(sne_ctx *ctx, const sne_frame *frames, int32_t n, int k
         // the slots' last batches ran on st: finish them before st goes away
         if (hipStreamSynchronize(st) != hipSuccess) rc = SNE_ERR_HIP;
     }
-    if (e0) hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
-    if (st) hipStreamDestroy(st);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
     if (rc != SNE_OK) return rc;
     ctx->cache[TileKey{maxH, maxW, kUnevenClass, kind, grad, agg, out_type}] = best;
     report_tile(best, tile);

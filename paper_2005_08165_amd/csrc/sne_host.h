@@ -16,6 +16,8 @@ namespace sne {
 
 constexpr int kVersion = 10000;  // 1.0.0
 constexpr int kSlots = 4;        // in-flight uneven batches per context
+constexpr int kEvalMaxPhis = 8;  // thresholds of sne_accuracy
+constexpr int kEvalRow = 2 + kEvalMaxPhis;  // per-block partials: sum psi, count, hits
 
 // Batch classes of the tile cache: 0 one frame, 1 up to 8, 2 more (uniform
 // batches), kUnevenClass shapes tuned on the persistent uneven-batch kernel.
@@ -90,6 +92,10 @@ struct sne_ctx {
     // servers created on this context: their scheduler threads read d_K, so
     // the table may not be replaced (nor the context destroyed) meanwhile
     std::atomic<int> n_servers{0};
+    // sne_accuracy: per-block partials (num_cu * 8 rows) and the event of the
+    // last call, which a call on another stream waits for before reusing them
+    double *d_eval = nullptr;
+    hipEvent_t eval_done = nullptr;
 };
 
 namespace sne {

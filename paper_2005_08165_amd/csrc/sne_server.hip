@@ -163,7 +163,7 @@ public:
         *bt.head = BatchHeader{};
         bt.head->nframes = (int32_t)nb;
         bt.head->ntiles = (int32_t)tiles;
-        hipSetDevice(ctx->device);
+        if (hipSetDevice(ctx->device) != hipSuccess) return SNE_ERR_HIP;
         hipError_t e;
         if (cfg.use_graphs) {
             if (s.graph_ktable != ctx->d_K) {  // the table moved: recapture
@@ -220,7 +220,9 @@ namespace sne {
 namespace {
 
 void worker_loop(sne_server *srv) {
-    hipSetDevice(srv->ctx->device);
+    // the device was usable when the server was created; a failure here
+    // surfaces as failed batches
+    (void)hipSetDevice(srv->ctx->device);
     while (!srv->stop.load(std::memory_order_relaxed)) {
         bool busy;
         {
@@ -279,7 +281,7 @@ int sne_server_create(sne_server **out, sne_ctx *ctx, const sne_server_config *c
     if (!out) return SNE_ERR_ARG;
     *out = nullptr;
     if (!ctx || !cfg || !valid_config(*cfg)) return SNE_ERR_ARG;
-    hipSetDevice(ctx->device);
+    if (hipSetDevice(ctx->device) != hipSuccess) return SNE_ERR_HIP;
     sne_server *s = new sne_server();
     s->ctx = ctx;
     s->cfg = *cfg;

@@ -135,6 +135,8 @@ _SIGS = {
     "sne_autotune_batched": ([_vp, ctypes.POINTER(FrameDesc), _i32, _int, _int, _int, _int,
                               ctypes.POINTER(Tile)], _int),
     "sne_autotune_save": ([_vp, ctypes.c_char_p], _int),
+    "sne_accuracy": ([_vp, _vp, _int, _vp, _vp, _i32, ctypes.c_int64,
+                      ctypes.POINTER(ctypes.c_float), _i32, _vp, _vp], _int),
     "sne_autotune_load": ([_vp, ctypes.c_char_p], _int),
     "sne_server_create": ([ctypes.POINTER(_vp), _vp, ctypes.POINTER(ServerConfig)], _int),
     "sne_server_submit": ([_vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)], _int),
@@ -268,6 +270,32 @@ class Context:
                                          _enum(GRAD, grad, "grad"), _enum(AGG, agg, "agg"),
                                          _enum(OUT, out, "out"), ctypes.byref(t)))
         return t.cols_per_lane, t.rows, t.lanes
+
+    def accuracy(self, normals: torch.Tensor, gt: torch.Tensor,
+                 mask: Optional[torch.Tensor] = None, phis=(11.25, 22.5, 30.0), stream=None):
+        """sne_accuracy: (e_A, [e_P(phi) ...], m) of eq. ea_ep for normals
+        [..., 3, H, W] (FP32 or FP16) against ground truth [..., 3, H, W]
+        (FP32) over the pixels where mask [..., H, W] is non-zero.  Waits for
+        the result."""
+        if normals.dtype not in (torch.float32, torch.float16) or gt.dtype != torch.float32:
+            raise TypeError("normals FP32/FP16 and ground truth FP32 expected")
+        if normals.shape != gt.shape or normals.shape[-3] != 3:
+            raise ValueError("normals and ground truth must both be [..., 3, H, W]")
+        if not (normals.is_contiguous() and gt.is_contiguous()):
+            raise ValueError("contiguous tensors expected")
+        frame_px = normals.shape[-1] * normals.shape[-2]
+        B = normals.numel() // (3 * frame_px) if frame_px else 0
+        if mask is not None:
+            if mask.dtype != torch.uint8 or not mask.is_contiguous() or mask.numel() != B * frame_px:
+                raise ValueError("mask must be a contiguous uint8 [..., H, W]")
+        ph = (ctypes.c_float * max(len(phis), 1))(*[float(p) for p in phis])
+        res = torch.empty(2 + len(phis), dtype=torch.float64, device=normals.device)
+        check("sne_accuracy",
+              lib().sne_accuracy(self._h, normals.data_ptr(), 1 if normals.dtype == torch.float16
+                                 else 0, gt.data_ptr(), _ptr(mask), B, frame_px, ph, len(phis),
+                                 res.data_ptr(), _stream(stream)))
+        r = res.cpu().tolist()
+        return r[0], r[2:], int(r[1])
 
     def autotune_save(self, path: str):
         check("sne_autotune_save", lib().sne_autotune_save(self._h, path.encode()))

@@ -77,6 +77,7 @@ def test_null_context_errors():
     assert L.sne_set_intrinsics_table(None, None, 1) == -1
     assert L.sne_autotune(None, 10, 10, 1, 0, 0, 0, 0, None) == -1
     assert L.sne_autotune_batched(None, None, 1, 0, 0, 0, 0, None) == -1
+    assert L.sne_accuracy(None, None, 0, None, None, 0, 0, None, 0, None, None) == -1
     assert L.sne_autotune_save(None, b"/tmp/x") == -1
     assert L.sne_ctx_destroy(None) == 0
     assert L.sne_ctx_create(None, 0) == -1
