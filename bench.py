@@ -278,10 +278,19 @@ def cpu_baseline(host_batch, K, grad, agg, min_s=10.0, budget_s=20.0):
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
+    # one thread as well, for scale against a single-threaded CPU implementation
+    one, t1 = 0, time.perf_counter()
+    while time.perf_counter() - t1 < 3.0:
+        oracle.estimate(host_batch[one % host_batch.shape[0]], "depth_f32", K32, grad, agg,
+                        threads=1)
+        one += 1
+    dt1 = time.perf_counter() - t1
     return {"value": round(done * H * W / dt / 1e6, 2), "unit": "Mpix/s", "cores": threads,
             "kind": "oracle",
             "sample": "%d frames (%dx%d; passes over the %d frames of one batch), FP64, "
-                      "OpenMP over rows, %.1f s" % (done, H, W, host_batch.shape[0], dt)}
+                      "OpenMP over rows, %.1f s" % (done, H, W, host_batch.shape[0], dt),
+            "single_thread_value": round(one * H * W / dt1 / 1e6, 2),
+            "single_thread_sample": "%d frames, 1 thread, %.1f s" % (one, dt1)}
 
 
 def main():

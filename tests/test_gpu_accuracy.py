@@ -106,6 +106,8 @@ def test_accuracy_without_mask_and_empty():
     assert ctx.accuracy(z, z, None, (1.0,)) == (0.0, [0.0], 0)
     mz = torch.zeros((2, 40, 50), dtype=torch.uint8, device="cuda")
     assert ctx.accuracy(est, gt, mz, (1.0,)) == (0.0, [0.0], 0)
+    eA0, eP0, m0 = ctx.accuracy(est, gt, None, ())  # no thresholds
+    assert eP0 == [] and m0 == m and abs(eA0 - eA) <= 1e-12
 
 
 def test_accuracy_calls_on_two_streams():
