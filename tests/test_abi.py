@@ -155,3 +155,18 @@ def test_c_client_builds(tmp_path):
     import oracle
     oracle.build(force=False)
     assert os.path.exists(c_client_build.build())
+
+
+def test_header_compiles_as_c99(tmp_path):
+    """include/sne.h is a C header: plain C99 with -Wall -Wextra -pedantic."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no gcc")
+    src = tmp_path / "t.c"
+    src.write_text('#include "sne.h"\nint main(void) { return sne_version() > 0 ? 0 : 1; }\n')
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    r = subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                        "-fsyntax-only", "-I" + inc, str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
