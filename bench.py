@@ -188,7 +188,7 @@ def accuracy_eval(torch, S, sne, reps=100, phis=(11.25, 22.5, 30.0)):
             "frac_of_peak": round(px * 25 * reps / ev / 1e9 / PEAK_HBM_GBS, 4)}
 
 
-def serving(torch, S, sne, duration=2.0, slo_p99_ms=2.0, plain_run=True,
+def serving(torch, S, sne, duration=2.0, slo_p99_ms=2.0, plain_run=True, max_inflight=3,
             plan=(("mean", (20000, 60000, 100000, 120000, 140000, 160000)),
                   ("median", (20000, 60000, 100000, 120000, 140000)))):
     """64 sensor streams (resolution per stream drawn with seed 5001 from
@@ -216,7 +216,7 @@ def serving(torch, S, sne, duration=2.0, slo_p99_ms=2.0, plain_run=True,
     if plain_run:
         plan += (("mean", (60000,), False),)
     for agg, rates, graphs in plan:
-        srv = sne.Server(ctx, "depth_u16", "fd", agg, "f16", max_inflight=3,
+        srv = sne.Server(ctx, "depth_u16", "fd", agg, "f16", max_inflight=max_inflight,
                          max_batch_frames=256, hbm_budget_bytes=16 << 30, use_graphs=graphs)
         for lam in rates:
             log("serving FD-%s at %d frames/s%s" % (agg, lam, "" if graphs else ", no graphs"))
