@@ -184,6 +184,14 @@ def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
     return None if t is None else t.data_ptr()
 
 
+def _on_gpu(*tensors) -> None:
+    """Every tensor the library reads or writes must live in device memory:
+    a host pointer handed to a kernel would fault the GPU."""
+    for t in tensors:
+        if t is not None and not t.is_cuda:
+            raise ValueError("tensors passed to the library must be on the GPU, got %s" % t.device)
+
+
 def _stream(stream) -> Optional[int]:
     if stream is None:
         return torch.cuda.current_stream().cuda_stream
@@ -277,6 +285,7 @@ class Context:
         [..., 3, H, W] (FP32 or FP16) against ground truth [..., 3, H, W]
         (FP32) over the pixels where mask [..., H, W] is non-zero.  Waits for
         the result."""
+        _on_gpu(normals, gt, mask)
         if normals.dtype not in (torch.float32, torch.float16) or gt.dtype != torch.float32:
             raise TypeError("normals FP32/FP16 and ground truth FP32 expected")
         if normals.shape != gt.shape or normals.shape[-3] != 3:
@@ -335,6 +344,7 @@ class Context:
                      for f in frames]
         descs = (FrameDesc * n)()
         for i, f in enumerate(frames):
+            _on_gpu(f, normals[i], masks[i])
             if f.dtype != KIND_DTYPE[kind_i]:
                 raise TypeError("frame %d: kind %s needs %s" % (i, kind, KIND_DTYPE[kind_i]))
             H, W = f.shape[-2:]
@@ -381,6 +391,7 @@ class Server:
         self._keep = {}   # ticket -> input tensor kept alive until completion
 
     def submit(self, frame: torch.Tensor, stream_id: int, t_arrival: float = -1.0) -> int:
+        _on_gpu(frame)
         if frame.dtype != KIND_DTYPE[self.kind]:
             raise TypeError("server kind needs %s frames" % KIND_DTYPE[self.kind])
         H, W = frame.shape
@@ -442,6 +453,7 @@ class Server:
             Hs[s_], Ws[s_] = fs[0].shape
             Ps[s_] = _row_pitch(fs[0])
             for k, f in enumerate(fs):
+                _on_gpu(f)
                 if tuple(f.shape) != (Hs[s_], Ws[s_]) or f.dtype != KIND_DTYPE[self.kind]:
                     raise ValueError("stream %d: frames differ in shape or dtype" % s_)
                 ptrs[s_ * ring + k] = f.data_ptr()
@@ -509,6 +521,7 @@ def _hip():
 
 
 def _outputs(raw, out_i, normals, mask, want_mask):
+    _on_gpu(raw, normals, mask)
     shape = tuple(raw.shape[:-2]) + (3,) + tuple(raw.shape[-2:])
     if normals is None:
         normals = torch.empty(shape, dtype=OUT_DTYPE[out_i], device=raw.device)

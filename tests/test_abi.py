@@ -170,3 +170,14 @@ def test_header_compiles_as_c99(tmp_path):
     r = subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
                         "-fsyntax-only", "-I" + inc, str(src)], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+def test_binding_rejects_host_tensors():
+    """A host tensor's pointer handed to a kernel would fault the GPU: the
+    binding refuses host tensors before calling the library."""
+    import torch
+    raw = torch.ones((8, 8))
+    with pytest.raises(ValueError, match="on the GPU"):
+        sne.estimate(raw, (8.0, 8.0, 3.5, 3.5), "depth_f32")
+    with pytest.raises(ValueError, match="on the GPU"):
+        sne.estimate_uniform(raw[None], (8.0, 8.0, 3.5, 3.5), "depth_f32")
