@@ -141,7 +141,8 @@ int sne_set_intrinsics_table(sne_ctx *ctx, const sne_intrinsics *K, int32_t n);
 
 /* n frames of any sizes (host array of descriptors) in ONE persistent launch:
  * a grid sized to the GPU pulls tiles from eight device queues (one per XCD,
- * contiguous tile ranges) until every tile of every frame is done.  All frames share kind, grad, agg and out type.
+ * contiguous tile ranges) until every tile of every frame is done.  All
+ * frames share kind, grad, agg and out type.
  * Bitwise identical, frame by frame, to sne_estimate with the same K.
  * n = 0 launches nothing (frames may then be NULL).
  * The descriptor table is staged through pinned memory owned by the context,
@@ -174,10 +175,10 @@ int sne_get_tile(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int gr
 
 /* Time every candidate tile shape on an H x W x B workload of this variant
  * (synthetic planar input in scratch buffers the call allocates and frees;
- * up to 8 sets of input and outputs, at least 1 GB together, are used in turn
- * so that launches read and write HBM rather than the last-level cache), keep the
- * fastest in ctx's cache for the frame-size class of H x W, and report it
- * (tile may be NULL).  Synchronous; seconds at most. */
+ * up to 8 sets of input and outputs, at least 1 GB together, are used in
+ * turn so that launches read and write HBM rather than the last-level cache),
+ * keep the fastest in ctx's cache for the frame-size class of H x W, and
+ * report it (tile may be NULL).  Synchronous; seconds at most. */
 int sne_autotune(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int grad, int agg,
                  int out_type, sne_tile *tile);
 
