@@ -202,12 +202,13 @@ int sne_accuracy(sne_ctx *ctx, const void *normals, int out_type, const float *g
         const int64_t units = vec4 ? npx / 4 : npx;
         const int g = (int)std::max<int64_t>(
             1, std::min<int64_t>(max_blocks, (units + kEvalBlock - 1) / kEvalBlock));
+        const dim3 gd(g), bd(kEvalBlock);
         if (out_type == SNE_OUT_F16) {
-            if (vec4) hipLaunchKernelGGL((eval_partial<OUT_F16, 4>), dim3(g), dim3(kEvalBlock), 0, st, a);
-            else hipLaunchKernelGGL((eval_partial<OUT_F16, 1>), dim3(g), dim3(kEvalBlock), 0, st, a);
+            if (vec4) hipLaunchKernelGGL((eval_partial<OUT_F16, 4>), gd, bd, 0, st, a);
+            else hipLaunchKernelGGL((eval_partial<OUT_F16, 1>), gd, bd, 0, st, a);
         } else {
-            if (vec4) hipLaunchKernelGGL((eval_partial<OUT_F32, 4>), dim3(g), dim3(kEvalBlock), 0, st, a);
-            else hipLaunchKernelGGL((eval_partial<OUT_F32, 1>), dim3(g), dim3(kEvalBlock), 0, st, a);
+            if (vec4) hipLaunchKernelGGL((eval_partial<OUT_F32, 4>), gd, bd, 0, st, a);
+            else hipLaunchKernelGGL((eval_partial<OUT_F32, 1>), gd, bd, 0, st, a);
         }
         grid = g;
         if (hipGetLastError() != hipSuccess) return SNE_ERR_HIP;
