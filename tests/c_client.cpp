@@ -163,6 +163,49 @@ int main() {
     }
     std::printf("uneven batch of 3 == single frames (bitwise)\n");
 
+    // 3. the batched autotuner: a valid shape, and the batch run with it still
+    //    equals the single frames bitwise
+    sne_tile tt{};
+    CHECK(sne_autotune_batched(ctx, frames.data(), 3, SNE_DEPTH_F32, SNE_GRAD_SOBEL,
+                               SNE_AGG_MEDIAN, SNE_OUT_F32, &tt) == SNE_OK);
+    CHECK((tt.cols_per_lane == 1 || tt.cols_per_lane == 2 || tt.cols_per_lane == 4) &&
+          tt.rows >= 1 && (tt.lanes == 32 || tt.lanes == 64));
+    CHECK(sne_estimate_batched(ctx, frames.data(), 3, SNE_DEPTH_F32, SNE_GRAD_SOBEL,
+                               SNE_AGG_MEDIAN, SNE_OUT_F32, st) == SNE_OK);
+    HIPOK(hipStreamSynchronize(st));
+    for (int f = 0; f < 3; ++f) {
+        const size_t n = (size_t)Hs[f] * Ws[f];
+        std::vector<float> bn(3 * n), sn;
+        std::vector<uint8_t> bm(n), sm;
+        HIPOK(hipMemcpy(bn.data(), d_n[f], 3 * n * 4, hipMemcpyDeviceToHost));
+        HIPOK(hipMemcpy(bm.data(), d_m[f], n, hipMemcpyDeviceToHost));
+        run_single(ctx, zs[f], Hs[f], Ws[f], Ks[f], st, sn, sm);
+        CHECK(std::memcmp(bn.data(), sn.data(), 3 * n * 4) == 0);
+        CHECK(std::memcmp(bm.data(), sm.data(), n) == 0);
+    }
+    std::printf("tuned uneven batch (%d x %d rows, %d lanes) == single frames (bitwise)\n",
+                tt.cols_per_lane, tt.rows, tt.lanes);
+
+    // 4. accuracy metrics: a frame's normals against themselves have psi = 0
+    //    at every masked-in pixel
+    {
+        const size_t n = (size_t)Hs[1] * Ws[1];
+        std::vector<uint8_t> hm(n);
+        HIPOK(hipMemcpy(hm.data(), d_m[1], n, hipMemcpyDeviceToHost));
+        size_t valid = 0;
+        for (uint8_t v : hm) valid += v != 0;
+        double *d_res = nullptr, res[3] = {-1, -1, -1};
+        HIPOK(hipMalloc(&d_res, sizeof(res)));
+        const float phi0 = 0.f;
+        CHECK(sne_accuracy(ctx, d_n[1], SNE_OUT_F32, d_n[1], d_m[1], 1, (int64_t)n, &phi0, 1,
+                           d_res, st) == SNE_OK);
+        HIPOK(hipStreamSynchronize(st));
+        HIPOK(hipMemcpy(res, d_res, sizeof(res), hipMemcpyDeviceToHost));
+        HIPOK(hipFree(d_res));
+        CHECK(res[0] == 0.0 && res[1] == (double)valid && res[2] == 1.0);
+        std::printf("accuracy of a frame against itself: e_A 0, m %zu, e_P(0) 1\n", valid);
+    }
+
     // 3. the serving loop: the same frames as requests, results in the arena
     sne_server_config cfg{SNE_DEPTH_F32, SNE_GRAD_SOBEL, SNE_AGG_MEDIAN, SNE_OUT_F32,
                           2, 16, 1 << 24, 64 << 20, 64, 1, 0};
