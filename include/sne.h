@@ -135,6 +135,9 @@ typedef struct {
 
 /* Copy n intrinsics records (host memory) into the context's device-resident
  * table, replacing it; frames of sne_estimate_batched refer to its rows.
+ * Every row needs finite values and fx, fy > 0; rows used with disparity
+ * input also need fx == fy, which the calls that use them check.  The context
+ * keeps a host copy for those checks.
  * Waits for the context's own batches; SNE_ERR_STATE while a server created
  * on ctx exists (its batches read the table when they run). */
 int sne_set_intrinsics_table(sne_ctx *ctx, const sne_intrinsics *K, int32_t n);
@@ -144,6 +147,10 @@ int sne_set_intrinsics_table(sne_ctx *ctx, const sne_intrinsics *K, int32_t n);
  * contiguous tile ranges) until every tile of every frame is done.  All
  * frames share kind, grad, agg and out type.
  * Bitwise identical, frame by frame, to sne_estimate with the same K.
+ * SNE_ERR_ARG when a frame's k_index names no row of the table or, for
+ * disparity input, a row with fx != fy (the disparity form needs f = fx = fy,
+ * eq. z_d); nothing is launched then.  The grid holds what the GPU keeps
+ * resident of the kernel, and no more workgroups than the batch's tiles need.
  * n = 0 launches nothing (frames may then be NULL).
  * The descriptor table is staged through pinned memory owned by the context,
  * so the host array may be reused as soon as the call returns; a further call
@@ -245,6 +252,11 @@ typedef struct {
     int32_t stream_id;     /* sensor stream = row of the intrinsics table    */
     int32_t reserved;      /* must be 0 */
     double t_arrival;      /* seconds on the server clock; < 0: now          */
+    void *ready;           /* hipEvent_t recorded after the work that writes
+                              `in`, or NULL when `in` is already complete.
+                              The batch's stream waits for it before reading
+                              the frame; the event must stay alive (and not be
+                              recorded again) until the request completes.   */
 } sne_request;
 
 typedef struct {
@@ -272,7 +284,11 @@ typedef struct {
  * else the one for uniform batches, else the built-in heuristic; it is fixed
  * when the server is created. */
 int sne_server_create(sne_server **out, sne_ctx *ctx, const sne_server_config *cfg);
-/* Thread-safe.  SNE_ERR_BUDGET: the frame's outputs exceed the whole arena;
+/* Thread-safe.  The frame must stay unchanged until the request completes;
+ * writes to it that are still in flight on some stream are ordered before the
+ * batch only through req->ready.  SNE_ERR_ARG also when stream_id names no
+ * row of the table or, for disparity input, a row with fx != fy (eq. z_d).
+ * SNE_ERR_BUDGET: the frame's outputs exceed the whole arena;
  * SNE_ERR_FULL: queue_capacity requests are already waiting (retry). */
 int sne_server_submit(sne_server *srv, const sne_request *req, uint64_t *ticket);
 /* Up to max finished requests (oldest first); *n receives the count. */

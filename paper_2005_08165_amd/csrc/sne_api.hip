@@ -31,6 +31,11 @@ bool valid_K(const sne_intrinsics *K, int kind) {
     return true;
 }
 
+bool valid_K_row(const sne_ctx *ctx, int32_t k, int kind) {
+    if (k < 0 || k >= ctx->nK || (size_t)k >= ctx->h_K.size()) return false;
+    return valid_K(&ctx->h_K[k], kind);
+}
+
 size_t in_elem(int kind) { return kind == SNE_DEPTH_F32 || kind == SNE_DISPARITY_F32 ? 4 : 2; }
 size_t out_elem(int out) { return out == SNE_OUT_F32 ? 4 : 2; }
 
@@ -130,6 +135,35 @@ hipError_t launch_batch(const Variant &v, const BatchArgs &a, int grid, hipStrea
     }
 }
 
+hipError_t occupancy_batch(const Variant &v, int *blocks) {
+    switch (v.kind) {
+    case SNE_DEPTH_F32: return occupancy_batch_f32(v, blocks);
+    case SNE_DEPTH_U16: return occupancy_batch_u16(v, blocks);
+    case SNE_DEPTH_F16: return occupancy_batch_f16(v, blocks);
+    default: return occupancy_batch_disp(v, blocks);
+    }
+}
+
+hipError_t batch_grid(sne_ctx *ctx, const Variant &v, int64_t tiles, int chunk, int *grid) {
+    // one instantiation per (kind, FD or 3-row filter, agg, out, px class);
+    // a fixed table, so that no call after the first allocates anything
+    const int pxi = (v.px % 100 == 4 ? 2 : v.px % 100 == 2 ? 1 : 0) + (v.px >= 100 ? 3 : 0);
+    const int key =
+        (((v.kind * 2 + (v.grad == SNE_GRAD_FD ? 0 : 1)) * 2 + v.agg) * 2 + v.out) * 6 + pxi;
+    if (key < 0 || key >= kOccEntries) return hipErrorInvalidValue;
+    int per_cu = ctx->occ[key].load(std::memory_order_relaxed);
+    if (per_cu == 0) {
+        const hipError_t e = occupancy_batch(v, &per_cu);
+        if (e != hipSuccess) return e;
+        per_cu = std::max(per_cu, 1);
+        ctx->occ[key].store(per_cu, std::memory_order_relaxed);
+    }
+    const int64_t per_block = (int64_t)chunk * kWavesPerBlock;
+    const int64_t want = (tiles + per_block - 1) / per_block;
+    *grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)ctx->num_cu * per_cu));
+    return hipSuccess;
+}
+
 FrameDesc make_desc(const void *in, void *out, uint8_t *mask, int H, int W, int64_t in_pitch,
                     int64_t out_pitch, int64_t mask_pitch, const sne_intrinsics &K) {
     FrameDesc f;
@@ -149,6 +183,29 @@ FrameDesc make_desc(const void *in, void *out, uint8_t *mask, int H, int W, int6
     f.k_index = 0;
     f.pad_ = 0;
     return f;
+}
+
+// Validate every descriptor of an uneven batch (before anything touches the
+// GPU) and find the largest frame and the widest vector width all allow.
+int scan_batch(const sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int out_type,
+               int &maxH, int &maxW, int &pxmax) {
+    pxmax = 4;
+    maxH = maxW = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const sne_frame &f = frames[i];
+        if (!f.in || !f.normals || f.H < 1 || f.W < 1 || f.in_pitch < f.W ||
+            f.out_pitch < f.W || (f.mask && f.mask_pitch < f.W) || f.reserved != 0)
+            return SNE_ERR_ARG;
+        if (!valid_K_row(ctx, f.k_index, kind)) return SNE_ERR_ARG;
+        if (!frame_fits(f.H, f.in_pitch, kind, f.out_pitch, out_type, f.mask ? f.mask_pitch : 0))
+            return SNE_ERR_UNSUPPORTED;
+        pxmax = std::min(pxmax, max_px(f.in, f.normals, f.mask, f.W, f.in_pitch, f.out_pitch,
+                                       f.mask_pitch, 0, 0, 0, (int64_t)f.H * f.out_pitch, kind,
+                                       out_type));
+        maxH = std::max(maxH, (int)f.H);
+        maxW = std::max(maxW, (int)f.W);
+    }
+    return SNE_OK;
 }
 
 namespace {
@@ -230,29 +287,6 @@ int ensure_slot(Slot &s, size_t n) {
     return SNE_OK;
 }
 
-// Validate every descriptor of an uneven batch (before anything touches the
-// GPU) and find the largest frame and the widest vector width all allow.
-int scan_batch(const sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int out_type,
-               int &maxH, int &maxW, int &pxmax) {
-    pxmax = 4;
-    maxH = maxW = 0;
-    for (int32_t i = 0; i < n; ++i) {
-        const sne_frame &f = frames[i];
-        if (!f.in || !f.normals || f.H < 1 || f.W < 1 || f.in_pitch < f.W ||
-            f.out_pitch < f.W || (f.mask && f.mask_pitch < f.W) || f.reserved != 0)
-            return SNE_ERR_ARG;
-        if (f.k_index < 0 || f.k_index >= ctx->nK) return SNE_ERR_ARG;
-        if (!frame_fits(f.H, f.in_pitch, kind, f.out_pitch, out_type, f.mask ? f.mask_pitch : 0))
-            return SNE_ERR_UNSUPPORTED;
-        pxmax = std::min(pxmax, max_px(f.in, f.normals, f.mask, f.W, f.in_pitch, f.out_pitch,
-                                       f.mask_pitch, 0, 0, 0, (int64_t)f.H * f.out_pitch, kind,
-                                       out_type));
-        maxH = std::max(maxH, (int)f.H);
-        maxW = std::max(maxW, (int)f.W);
-    }
-    return SNE_OK;
-}
-
 int batched_impl(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int grad, int agg,
                  int out_type, void *stream, const TileChoice *force) {
     if (!ctx || n < 0 || !valid_enum(kind, grad, agg, out_type)) return SNE_ERR_ARG;
@@ -302,11 +336,10 @@ int batched_impl(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int
     a.rows = t.rows;
     a.chunk = 1;
     grad_weights(grad, a.wa, a.wb);
-    const int64_t want = (tiles + (int64_t)a.chunk * kWavesPerBlock - 1) /
-                         ((int64_t)a.chunk * kWavesPerBlock);
-    const int occ = ctx->occ_blocks > 0 ? ctx->occ_blocks : 8;
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)ctx->num_cu * occ));
-    hipError_t e = launch_batch(v, a, grid, st);
+    int grid = 0;
+    hipError_t e = batch_grid(ctx, v, tiles, a.chunk, &grid);
+    if (e != hipSuccess) return SNE_ERR_HIP;
+    e = launch_batch(v, a, grid, st);
     if (e != hipSuccess) return SNE_ERR_HIP;
     if (hipEventRecord(s.done, st) != hipSuccess) return SNE_ERR_HIP;
     s.used = true;
@@ -448,7 +481,6 @@ int sne_ctx_create(sne_ctx **out, int device) {
         c->num_cu = prop.multiProcessorCount;
         c->arch = prop.gcnArchName;
     }
-    c->occ_blocks = 8;
     *out = c;
     return SNE_OK;
 }
@@ -508,6 +540,7 @@ int sne_set_intrinsics_table(sne_ctx *ctx, const sne_intrinsics *K, int32_t n) {
     }
     if (hipMemcpy(ctx->d_K, K, n * sizeof(sne_intrinsics), hipMemcpyHostToDevice) != hipSuccess)
         return SNE_ERR_HIP;
+    ctx->h_K.assign(K, K + n);
     ctx->nK = n;
     return SNE_OK;
 }

@@ -81,9 +81,13 @@ __global__ __launch_bounds__(kEvalBlock) void eval_partial(EvalArgs a) {
     const int64_t hwv = a.hw / V, nv = a.npx / V;  // in groups of V pixels
     const int64_t stride = (int64_t)gridDim.x * kEvalBlock;
     int64_t i = (int64_t)blockIdx.x * kEvalBlock + threadIdx.x;
-    // frame b and group q of i, advanced incrementally (no division per group)
+    // frame b and group q of i, advanced incrementally: the stride is sb
+    // whole frames plus sq groups (no division per group, and one carry at
+    // most however small the frames are)
     int64_t b = hwv > 0 ? i / hwv : 0;
     int64_t q = i - b * hwv;
+    const int64_t sb = hwv > 0 ? stride / hwv : 0;
+    const int64_t sq = stride - sb * hwv;
     const ET *est = static_cast<const ET *>(a.est);
     const GT *gt = reinterpret_cast<const GT *>(a.gt);
     const MT *mask = reinterpret_cast<const MT *>(a.mask);
@@ -105,8 +109,9 @@ __global__ __launch_bounds__(kEvalBlock) void eval_partial(EvalArgs a) {
                     if (j < a.nphi && psi <= a.phis[j]) hit[j] += 1.0;
             }
         }
-        q += stride;
-        while (q >= hwv) {
+        b += sb;
+        q += sq;
+        if (q >= hwv) {
             q -= hwv;
             ++b;
         }

@@ -6,15 +6,17 @@
 
 #include <atomic>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
+#include <vector>
 
 #include "sne.h"
 #include "sne_internal.h"
 
 namespace sne {
 
-constexpr int kVersion = 10000;  // 1.0.0
+constexpr int kVersion = 10100;  // 1.1.0
 constexpr int kSlots = 4;        // in-flight uneven batches per context
 constexpr int kEvalMaxPhis = 8;  // thresholds of sne_accuracy
 constexpr int kEvalRow = 2 + kEvalMaxPhis;  // per-block partials: sum psi, count, hits
@@ -22,6 +24,10 @@ constexpr int kEvalRow = 2 + kEvalMaxPhis;  // per-block partials: sum psi, coun
 // Batch classes of the tile cache: 0 one frame, 1 up to 8, 2 more (uniform
 // batches), kUnevenClass shapes tuned on the persistent uneven-batch kernel.
 constexpr int kUnevenClass = 3;
+
+// Persistent-kernel instantiations: 4 kinds x {FD, 3-row} x 2 agg x 2 out x
+// 6 column classes (1, 2, 4 columns per lane, full or half wave).
+constexpr int kOccEntries = 4 * 2 * 2 * 2 * 6;
 
 struct TileKey {
     int H, W, bclass, kind, grad, agg, out;
@@ -55,6 +61,8 @@ struct Slot {
 
 bool valid_enum(int kind, int grad, int agg, int out);
 bool valid_K(const sne_intrinsics *K, int kind);
+// Row k of ctx's intrinsics table exists and suits the input kind.
+bool valid_K_row(const sne_ctx *ctx, int32_t k, int kind);
 size_t in_elem(int kind);
 size_t out_elem(int out_type);
 
@@ -77,6 +85,17 @@ FrameDesc make_desc(const void *in, void *out, uint8_t *mask, int H, int W, int6
 hipError_t launch_batch(const Variant &v, const BatchArgs &a, int grid, hipStream_t s);
 
 }  // namespace sne
+struct sne_ctx;
+namespace sne {
+// Workgroups of a persistent launch over `tiles` tiles: what the GPU holds at
+// once for this instantiation, and no more than the tiles need.
+hipError_t batch_grid(sne_ctx *ctx, const Variant &v, int64_t tiles, int chunk, int *grid);
+// Validate every descriptor of an uneven batch (host only) and find the
+// largest frame and the widest vector width all frames allow.
+int scan_batch(const sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int out_type,
+               int &maxH, int &maxW, int &pxmax);
+
+}  // namespace sne
 
 struct sne_ctx {
     int device = 0;
@@ -86,9 +105,14 @@ struct sne_ctx {
     std::map<sne::TileKey, sne::TileChoice> cache;
     sne_intrinsics *d_K = nullptr;
     int32_t nK = 0;
+    // host copy of the table: the disparity form needs fx == fy in every row
+    // a frame refers to, which is checked before anything is launched
+    std::vector<sne_intrinsics> h_K;
     sne::Slot slots[sne::kSlots];
     int next_slot = 0;
-    int occ_blocks = 0;  // resident workgroups per CU for the persistent grid
+    // resident workgroups per CU of each persistent-kernel instantiation
+    // (queried on first use; the server's scheduler thread reads it too)
+    std::atomic<int> occ[sne::kOccEntries] = {};
     // servers created on this context: their scheduler threads read d_K, so
     // the table may not be replaced (nor the context destroyed) meanwhile
     std::atomic<int> n_servers{0};

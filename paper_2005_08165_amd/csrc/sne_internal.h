@@ -67,7 +67,7 @@ struct BatchTable {
     int32_t *nstrips;
 };
 
-__host__ __device__ inline size_t batch_table_bytes(int64_t nframes) {
+__host__ __device__ constexpr inline size_t batch_table_bytes(int64_t nframes) {
     return sizeof(BatchHeader) + (size_t)nframes * sizeof(FrameDesc) +
            (size_t)(2 * nframes + 1) * sizeof(int32_t);
 }
@@ -108,6 +108,11 @@ hipError_t launch_batch_f32(const Variant &v, const BatchArgs &a, int grid, hipS
 hipError_t launch_batch_u16(const Variant &v, const BatchArgs &a, int grid, hipStream_t s);
 hipError_t launch_batch_f16(const Variant &v, const BatchArgs &a, int grid, hipStream_t s);
 hipError_t launch_batch_disp(const Variant &v, const BatchArgs &a, int grid, hipStream_t s);
+// Resident workgroups per CU of the persistent kernel's instantiation.
+hipError_t occupancy_batch_f32(const Variant &v, int *blocks);
+hipError_t occupancy_batch_u16(const Variant &v, int *blocks);
+hipError_t occupancy_batch_f16(const Variant &v, int *blocks);
+hipError_t occupancy_batch_disp(const Variant &v, int *blocks);
 
 // Kernel-side enum values (mirror include/sne.h).
 enum { KIND_F32 = 0, KIND_U16 = 1, KIND_F16 = 2, KIND_DISP = 3 };

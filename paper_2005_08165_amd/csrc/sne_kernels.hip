@@ -713,6 +713,15 @@ __global__ __launch_bounds__(kBlock) SNE_BATCH_OCCUPANCY void sne_batch_kernel(B
         const int q = (home + i) % kQueues;
         const int begin = (int)((int64_t)ntiles * q / kQueues);
         const int end = (int)((int64_t)ntiles * (q + 1) / kQueues);
+        // The counters only grow: a queue seen exhausted by a plain load is
+        // left without an atomic (a stale smaller value merely costs one),
+        // so the waves of a grid larger than the batch leave after a few
+        // reads instead of queueing eight atomics each on the same lines.
+        int seen = 0;
+        if (lane == 0)
+            seen = __hip_atomic_load(&head->queue[q].next, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+        if (__builtin_amdgcn_readfirstlane(seen) >= end - begin) continue;
         for (;;) {
             int taken = 0;
             if (lane == 0) taken = atomicAdd(&head->queue[q].next, a.chunk);
@@ -771,6 +780,21 @@ hipError_t batch_px(int px, const BatchArgs &a, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int KIND, bool FD, int AGG, int OUT>
+hipError_t occupancy_px(int px, int *blocks) {
+    const void *f = nullptr;
+    switch (px) {
+    case 1: f = reinterpret_cast<const void *>(&sne_batch_kernel<KIND, FD, AGG, OUT, 1, false>); break;
+    case 2: f = reinterpret_cast<const void *>(&sne_batch_kernel<KIND, FD, AGG, OUT, 2, false>); break;
+    case 4: f = reinterpret_cast<const void *>(&sne_batch_kernel<KIND, FD, AGG, OUT, 4, false>); break;
+    case 101: f = reinterpret_cast<const void *>(&sne_batch_kernel<KIND, FD, AGG, OUT, 1, true>); break;
+    case 102: f = reinterpret_cast<const void *>(&sne_batch_kernel<KIND, FD, AGG, OUT, 2, true>); break;
+    case 104: f = reinterpret_cast<const void *>(&sne_batch_kernel<KIND, FD, AGG, OUT, 4, true>); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, f, kBlock, 0);
+}
+
 #define SNE_DISPATCH(FN, ARGS)                                                              \
     template <int KIND>                                                                     \
     hipError_t FN##_variant(const Variant &v, const ARGS &a, int grid, hipStream_t s) {     \
@@ -791,6 +815,22 @@ hipError_t batch_px(int px, const BatchArgs &a, int grid, hipStream_t s) {
 
 SNE_DISPATCH(uniform, UniformArgs)
 SNE_DISPATCH(batch, BatchArgs)
+
+template <int KIND> hipError_t occupancy_variant(const Variant &v, int *blocks) {
+    const bool fd = v.grad == 0;
+    if (fd) {
+        if (v.agg == AGG_MEAN)
+            return v.out == OUT_F32 ? occupancy_px<KIND, true, AGG_MEAN, OUT_F32>(v.px, blocks)
+                                    : occupancy_px<KIND, true, AGG_MEAN, OUT_F16>(v.px, blocks);
+        return v.out == OUT_F32 ? occupancy_px<KIND, true, AGG_MEDIAN, OUT_F32>(v.px, blocks)
+                                : occupancy_px<KIND, true, AGG_MEDIAN, OUT_F16>(v.px, blocks);
+    }
+    if (v.agg == AGG_MEAN)
+        return v.out == OUT_F32 ? occupancy_px<KIND, false, AGG_MEAN, OUT_F32>(v.px, blocks)
+                                : occupancy_px<KIND, false, AGG_MEAN, OUT_F16>(v.px, blocks);
+    return v.out == OUT_F32 ? occupancy_px<KIND, false, AGG_MEDIAN, OUT_F32>(v.px, blocks)
+                            : occupancy_px<KIND, false, AGG_MEDIAN, OUT_F16>(v.px, blocks);
+}
 
 }  // namespace
 
@@ -814,6 +854,10 @@ hipError_t SNE_CAT(launch_uniform_, SNE_SUFFIX)(const Variant &v, const UniformA
 hipError_t SNE_CAT(launch_batch_, SNE_SUFFIX)(const Variant &v, const BatchArgs &a, int grid,
                                               hipStream_t s) {
     return batch_variant<SNE_KIND>(v, a, grid, s);
+}
+
+hipError_t SNE_CAT(occupancy_batch_, SNE_SUFFIX)(const Variant &v, int *blocks) {
+    return occupancy_variant<SNE_KIND>(v, blocks);
 }
 
 }  // namespace sne

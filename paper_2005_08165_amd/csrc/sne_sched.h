@@ -39,6 +39,7 @@ struct Request {
     int status = 0;
     const void *in = nullptr;  // the frame (read by the executor only)
     int64_t in_pitch = 0;      // its row pitch in elements
+    const void *ready = nullptr;  // event the frame's producer recorded, or null
 };
 
 struct Config {

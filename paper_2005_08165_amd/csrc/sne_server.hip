@@ -8,9 +8,10 @@
 // requests that arrive meanwhile go into the next batch.  Each slot owns its
 // pinned descriptor staging, its device tables and (optionally) a captured
 // hipGraph per columns-per-lane class: {staging -> device copy, persistent
-// kernel}; a batch rewrites the staging and replays the graph (the copy also
-// resets the kernel's tile queues).  Scheduling policy lives in sne_sched.cpp
-// (pure C++).
+// kernel}; a batch rewrites the staging, sets the copy's size and the
+// kernel's grid for the batch in the executable graph and replays it (the
+// copy also resets the kernel's tile queues).  The grid never exceeds what the
+// batch's tiles need.  Scheduling policy lives in sne_sched.cpp (pure C++).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,19 +32,38 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+// A captured batch: {table copy, persistent kernel}.  Before each replay the
+// copy's size and the kernel's grid are set for the batch at hand; the kernel
+// node's new parameters point at `args`, which lives as long as the slot (the
+// graph the executable came from is kept, as node updates name its nodes).
+struct GraphRes {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t copy = nullptr, kernel = nullptr;
+    hipKernelNodeParams kp{};
+    BatchArgs args{};
+    void *argv[1] = {nullptr};
+};
+
 struct SlotRes {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     void *h_stage = nullptr;   // pinned batch table (layout: BatchTable)
     void *d_stage = nullptr;   // device copy
     size_t bytes = 0;          // table size at full capacity
-    hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};  // px = 1, 2, 4
+    GraphRes graph[3];         // px = 1, 2, 4
     const void *graph_ktable = nullptr;
     bool launched = false;
     int rc = 0;
 };
 
 int px_index(int px) { return px == 4 ? 2 : (px == 2 ? 1 : 0); }
+
+void drop_graph(GraphRes &g) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g = GraphRes{};
+}
 
 class HipExecutor : public sched::Executor {
 public:
@@ -76,8 +96,7 @@ public:
     void destroy() {
         for (auto &s : slots) {
             if (s.stream) (void)hipStreamSynchronize(s.stream);
-            for (auto &g : s.graph)
-                if (g) (void)hipGraphExecDestroy(g);
+            for (auto &g : s.graph) drop_graph(g);
             if (s.done) (void)hipEventDestroy(s.done);
             if (s.stream) (void)hipStreamDestroy(s.stream);
             if (s.h_stage) (void)hipHostFree(s.h_stage);
@@ -96,37 +115,51 @@ public:
         return a;
     }
 
-    int grid() const {
-        const int occ = ctx->occ_blocks > 0 ? ctx->occ_blocks : 8;
-        return ctx->num_cu * occ;
-    }
-
     // The steps of one batch, enqueued on the slot's stream: the table copy
-    // (`bytes` of it; a captured graph copies the whole capacity) and the
-    // persistent kernel.
-    hipError_t enqueue(SlotRes &s, int kpx, size_t bytes) {
+    // (`bytes` of it; it also resets the tile queues) and the persistent
+    // kernel on `grid` workgroups.
+    hipError_t enqueue(SlotRes &s, int kpx, size_t bytes, int grid) {
         hipError_t e = hipMemcpyAsync(s.d_stage, s.h_stage, bytes, hipMemcpyHostToDevice,
                                       s.stream);
         if (e != hipSuccess) return e;
         Variant v{cfg.kind, cfg.grad, cfg.agg, cfg.out_type, kpx};
-        return launch_batch(v, args(s), grid(), s.stream);
+        return launch_batch(v, args(s), grid, s.stream);
     }
 
     int build_graph(SlotRes &s, const TileChoice &t) {
-        hipGraph_t g = nullptr;
-        hipGraphExec_t ex = nullptr;
+        GraphRes &gr = s.graph[px_index(t.px)];
         if (hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return SNE_ERR_HIP;
-        const hipError_t e = enqueue(s, kernel_px(t), s.bytes);
-        const hipError_t e2 = hipStreamEndCapture(s.stream, &g);
-        if (e != hipSuccess || e2 != hipSuccess || !g) {
-            if (g) (void)hipGraphDestroy(g);
+        const hipError_t e = enqueue(s, kernel_px(t), s.bytes, 1);
+        const hipError_t e2 = hipStreamEndCapture(s.stream, &gr.graph);
+        if (e != hipSuccess || e2 != hipSuccess || !gr.graph) {
+            drop_graph(gr);
             return SNE_ERR_HIP;
         }
-        const hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e3 != hipSuccess) return SNE_ERR_HIP;
-        s.graph[px_index(t.px)] = ex;
+        size_t n = 0;
+        hipGraphNode_t nodes[2] = {nullptr, nullptr};
+        if (hipGraphGetNodes(gr.graph, nullptr, &n) != hipSuccess || n != 2 ||
+            hipGraphGetNodes(gr.graph, nodes, &n) != hipSuccess) {
+            drop_graph(gr);
+            return SNE_ERR_HIP;
+        }
+        for (hipGraphNode_t nd : nodes) {
+            hipGraphNodeType ty;
+            if (hipGraphNodeGetType(nd, &ty) != hipSuccess) continue;
+            if (ty == hipGraphNodeTypeKernel) gr.kernel = nd;
+            if (ty == hipGraphNodeTypeMemcpy) gr.copy = nd;
+        }
+        if (!gr.kernel || !gr.copy ||
+            hipGraphKernelNodeGetParams(gr.kernel, &gr.kp) != hipSuccess ||
+            hipGraphInstantiate(&gr.exec, gr.graph, nullptr, nullptr, 0) != hipSuccess) {
+            drop_graph(gr);
+            return SNE_ERR_HIP;
+        }
+        // the kernel takes one argument, the BatchArgs of this slot
+        gr.args = args(s);
+        gr.argv[0] = &gr.args;
+        gr.kp.kernelParams = gr.argv;
+        gr.kp.extra = nullptr;
         return SNE_OK;
     }
 
@@ -158,27 +191,48 @@ public:
             bt.tile_start[i] = (int32_t)tiles;
             bt.nstrips[i] = nst;
             tiles += (int64_t)nst * nbands;
+            // tile indices are 32-bit in the kernel (as in sne_estimate_batched)
+            if (tiles > INT32_MAX / 2) return SNE_ERR_BUDGET;
         }
         bt.tile_start[nb] = (int32_t)tiles;
         *bt.head = BatchHeader{};
         bt.head->nframes = (int32_t)nb;
         bt.head->ntiles = (int32_t)tiles;
         if (hipSetDevice(ctx->device) != hipSuccess) return SNE_ERR_HIP;
+        const Variant v{cfg.kind, cfg.grad, cfg.agg, cfg.out_type, kernel_px(t)};
+        int grid = 0;
+        if (batch_grid(ctx, v, tiles, 1, &grid) != hipSuccess) return SNE_ERR_HIP;
+        // the batch's frames are read only once their producers are done
+        const void *last = nullptr;
+        for (auto *q : b.reqs) {
+            if (!q->ready || q->ready == last) continue;
+            last = q->ready;
+            if (hipStreamWaitEvent(s.stream, (hipEvent_t)const_cast<void *>(q->ready), 0) !=
+                hipSuccess)
+                return SNE_ERR_HIP;
+        }
+        const size_t used = batch_table_bytes(nb);
         hipError_t e;
         if (cfg.use_graphs) {
             if (s.graph_ktable != ctx->d_K) {  // the table moved: recapture
-                for (auto &g : s.graph)
-                    if (g) (void)hipGraphExecDestroy(g);
-                s.graph[0] = s.graph[1] = s.graph[2] = nullptr;
+                for (auto &g : s.graph) drop_graph(g);
                 s.graph_ktable = ctx->d_K;
             }
-            if (!s.graph[px_index(px)]) {
+            GraphRes &gr = s.graph[px_index(px)];
+            if (!gr.exec) {
                 const int rc = build_graph(s, t);
                 if (rc != SNE_OK) return rc;
             }
-            e = hipGraphLaunch(s.graph[px_index(px)], s.stream);
+            // the slot's previous replay has finished (the scheduler frees a
+            // slot only then), so its nodes may be changed
+            gr.kp.gridDim = dim3(grid);
+            e = hipGraphExecKernelNodeSetParams(gr.exec, gr.kernel, &gr.kp);
+            if (e == hipSuccess)
+                e = hipGraphExecMemcpyNodeSetParams1D(gr.exec, gr.copy, s.d_stage, s.h_stage, used,
+                                                      hipMemcpyHostToDevice);
+            if (e == hipSuccess) e = hipGraphLaunch(gr.exec, s.stream);
         } else {
-            e = enqueue(s, kernel_px(t), batch_table_bytes(nb));
+            e = enqueue(s, kernel_px(t), used, grid);
         }
         if (e != hipSuccess || hipEventRecord(s.done, s.stream) != hipSuccess) return SNE_ERR_HIP;
         s.launched = true;
@@ -319,7 +373,9 @@ int sne_server_submit(sne_server *srv, const sne_request *req, uint64_t *ticket)
     if (!srv || !req || !req->in || req->H < 1 || req->W < 1 || req->in_pitch < req->W ||
         req->reserved != 0)
         return SNE_ERR_ARG;
-    if (req->stream_id < 0 || req->stream_id >= srv->ctx->nK) return SNE_ERR_ARG;
+    // the table cannot change while the server exists (sne_set_intrinsics_table
+    // refuses), so reading its host copy from producer threads is safe
+    if (!valid_K_row(srv->ctx, req->stream_id, srv->cfg.kind)) return SNE_ERR_ARG;
     if (!frame_fits(req->H, req->in_pitch, srv->cfg.kind, req->W, srv->cfg.out_type, req->W))
         return SNE_ERR_UNSUPPORTED;
     sched::Request r;
@@ -329,6 +385,7 @@ int sne_server_submit(sne_server *srv, const sne_request *req, uint64_t *ticket)
     r.out_bytes = out_bytes(srv->cfg, req->H, req->W);
     r.in = req->in;
     r.in_pitch = req->in_pitch;
+    r.ready = req->ready;
     std::lock_guard<std::mutex> lk(srv->mu);
     r.t_arrival = req->t_arrival >= 0 ? req->t_arrival : srv->now();
     const int rc = srv->sched->submit(r, ticket);
@@ -461,6 +518,7 @@ int sne_server_run_open_loop(sne_server *srv, const sne_loadgen_config *cfg,
                 r.stream_id = a.stream;
                 r.reserved = 0;
                 r.t_arrival = when;  // latency counts from the scheduled arrival
+                r.ready = nullptr;   // the rings are filled before the run
                 uint64_t t;
                 if (sne_server_submit(srv, &r, &t) == SNE_OK)
                     submitted++;

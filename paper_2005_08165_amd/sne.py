@@ -69,7 +69,8 @@ class ServerConfig(ctypes.Structure):
 class Request(ctypes.Structure):
     _fields_ = [("input", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
                 ("in_pitch", ctypes.c_int64), ("stream_id", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("t_arrival", ctypes.c_double)]
+                ("reserved", ctypes.c_int32), ("t_arrival", ctypes.c_double),
+                ("ready", ctypes.c_void_p)]
 
 
 class Completion(ctypes.Structure):
@@ -200,6 +201,16 @@ def _stream(stream) -> Optional[int]:
     return int(stream)
 
 
+def _sync(stream) -> None:
+    """Wait for a torch stream or a raw hipStream_t handle."""
+    if isinstance(stream, torch.cuda.Stream):
+        stream.synchronize()
+        return
+    rc = _hip().hipStreamSynchronize(ctypes.c_void_p(int(stream)))
+    if rc != 0:
+        raise RuntimeError("hipStreamSynchronize failed (%d)" % rc)
+
+
 def _K(K: Sequence[float]) -> Intrinsics:
     fx, fy, u0, v0 = (float(x) for x in K)
     return Intrinsics(fx, fy, u0, v0)
@@ -303,6 +314,8 @@ class Context:
               lib().sne_accuracy(self._h, normals.data_ptr(), 1 if normals.dtype == torch.float16
                                  else 0, gt.data_ptr(), _ptr(mask), B, frame_px, ph, len(phis),
                                  res.data_ptr(), _stream(stream)))
+        if stream is not None:
+            _sync(stream)  # res was written there; read it only once it is done
         r = res.cpu().tolist()
         return r[0], r[2:], int(r[1])
 
@@ -390,15 +403,22 @@ class Server:
               lib().sne_server_create(ctypes.byref(self._h), ctx.handle, ctypes.byref(cfg)))
         self._keep = {}   # ticket -> input tensor kept alive until completion
 
-    def submit(self, frame: torch.Tensor, stream_id: int, t_arrival: float = -1.0) -> int:
+    def submit(self, frame: torch.Tensor, stream_id: int, t_arrival: float = -1.0,
+               producer=None) -> int:
+        """Queue one frame.  An event is recorded on `producer` (default: the
+        current stream), so the batch reads the frame only after the work
+        enqueued there so far; frame and event are kept until release."""
         _on_gpu(frame)
         if frame.dtype != KIND_DTYPE[self.kind]:
             raise TypeError("server kind needs %s frames" % KIND_DTYPE[self.kind])
         H, W = frame.shape
-        r = Request(frame.data_ptr(), H, W, _row_pitch(frame), int(stream_id), 0, float(t_arrival))
+        ev = torch.cuda.Event()
+        ev.record(producer if producer is not None else torch.cuda.current_stream(frame.device))
+        r = Request(frame.data_ptr(), H, W, _row_pitch(frame), int(stream_id), 0, float(t_arrival),
+                    ev.cuda_event)
         t = ctypes.c_uint64()
         check("sne_server_submit", lib().sne_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
-        self._keep[t.value] = frame
+        self._keep[t.value] = (frame, ev)
         return t.value
 
     def poll(self, max_n: int = 1024):
@@ -517,6 +537,7 @@ def _hip():
     if _hiplib is None:
         _hiplib = ctypes.CDLL("libamdhip64.so")
         _hiplib.hipMemcpyAsync.restype = ctypes.c_int
+        _hiplib.hipStreamSynchronize.restype = ctypes.c_int
     return _hiplib
 
 

@@ -214,7 +214,7 @@ int main() {
     CHECK(sne_set_intrinsics_table(ctx, Ks, 3) == SNE_ERR_STATE);  // locked while served
     uint64_t tickets[3];
     for (int f = 0; f < 3; ++f) {
-        const sne_request r{d_in[f], Hs[f], Ws[f], Ws[f], f, 0, -1.0};
+        const sne_request r{d_in[f], Hs[f], Ws[f], Ws[f], f, 0, -1.0, nullptr};
         CHECK(sne_server_submit(srv, &r, &tickets[f]) == SNE_OK);
     }
     CHECK(sne_server_drain(srv, 10.0) == SNE_OK);

@@ -18,7 +18,7 @@ def test_exports_every_declared_function():
 
 
 def test_version_and_status_strings():
-    assert sne.version() == 10000
+    assert sne.version() == 10100
     assert sne.status_string(0) == "ok"
     assert sne.status_string(-1) == "invalid argument"
     assert sne.status_string(12345) == "unknown status"

@@ -127,8 +127,46 @@ def test_open_loop_small():
     srv.close()
 
 
+@pytest.mark.parametrize("use_graphs", [True, False])
+def test_batches_of_changing_size_equal_single_frame(use_graphs):
+    """Bursts of 1, 6, 2, 5 and 1 frames, drained in between, so that every
+    slot runs several batches with different tile counts: the persistent grid
+    (and, with graphs, the replayed kernel's grid and table copy) changes from
+    batch to batch; every result stays bitwise equal to its single frame."""
+    cams, frames = _streams()
+    ctx = sne.Context(0)
+    ctx.set_intrinsics_table([c.as_tuple() for c in cams])
+    srv = sne.Server(ctx, "depth_u16", "fd", "median", "f16", max_inflight=2,
+                     max_batch_frames=16, hbm_budget_bytes=256 << 20, use_graphs=use_graphs)
+    singles = []
+    for s_, f in enumerate(frames):
+        singles.append(sne.estimate(f, cams[s_].as_tuple(), "depth_u16", "fd", "median", "f16"))
+    torch.cuda.synchronize()
+    order = [3, 0, 1, 2, 3, 4, 5, 5, 1, 0, 2, 3, 4, 5, 2]
+    bursts = [1, 6, 2, 5, 1]
+    k = 0
+    for b, n in enumerate(bursts):
+        say("burst", b, "of", n, "frames")
+        tickets = {srv.submit(frames[s_], s_): s_ for s_ in order[k:k + n]}
+        k += n
+        srv.drain()
+        done = srv.poll(64)
+        assert len(done) == n
+        for c in done:
+            assert c.status == 0
+            s_ = tickets[c.ticket]
+            nn, mm = srv.result(c)
+            assert torch.equal(nn, singles[s_][0]) and torch.equal(mm, singles[s_][1]), (b, s_)
+            srv.release(c.ticket)
+    assert srv.stats()["batches"] >= len(bursts)
+    srv.close()
+
+
 def test_served_4k_frames_equal_single_frame():
-    """The largest serving resolution (2160x3840) batched with small frames."""
+    """The largest serving resolution (2160x3840) batched with small frames.
+    The frames are rendered on the current stream and submitted without a
+    host synchronisation: the event each submit records orders the batch
+    after the rendering."""
     shapes = [(2160, 3840), (240, 320), (1080, 1920)]
     cams = [S.camera_for(h, w) for h, w in shapes]
     frames = [S.make_u16(6100 + i, c, device="cuda").raw for i, c in enumerate(cams)]
