@@ -236,10 +236,13 @@ KW = {"fd": (0, 1, 0), "sobel": (1, 2, 1), "scharr": (3, 10, 3), "prewitt": (1, 
 
 def gradients_vanish(raw_int, grad):
     """Pixels whose exact gradients G_u and G_v (rational arithmetic on 1/z)
-    are both zero although the window is not constant: there n' = 0 exactly
-    and the direction any floating-point evaluation returns, FP64 oracle
-    included, is its rounding noise, so no two evaluations can be compared.
-    FD has a single term per axis and never qualifies."""
+    are both zero by cancellation of non-zero filter lines: there n' = 0
+    exactly, while any floating-point evaluation, FP64 oracle included, keeps
+    a rounding residue whose sign sets the direction, so no two evaluations
+    can be compared.  Where every line difference is itself zero (equal raw
+    values; FD has one line per axis, so always) the floating-point
+    gradients are exactly zero too and the pixel is the well-defined
+    degenerate case: it is not flagged."""
     from fractions import Fraction as Fr
     H, W = raw_int.shape
     out = np.zeros((H, W), bool)
@@ -250,9 +253,10 @@ def gradients_vanish(raw_int, grad):
             if (win <= 0).any() or (win == win[1, 1]).all():
                 continue
             s = [[Fr(1, int(x)) for x in row] for row in win]
-            gu = sum(w[a] * (s[a][2] - s[a][0]) for a in range(3))
-            gv = sum(w[b] * (s[2][b] - s[0][b]) for b in range(3))
-            out[v, u] = gu == 0 and gv == 0
+            lu = [w[a] * (s[a][2] - s[a][0]) for a in range(3)]
+            lv = [w[b] * (s[2][b] - s[0][b]) for b in range(3)]
+            cancels = any(x != 0 for x in lu + lv)
+            out[v, u] = sum(lu) == 0 and sum(lv) == 0 and cancels
     return out
 
 
