@@ -158,6 +158,25 @@ int sne_set_intrinsics_table(sne_ctx *ctx, const sne_intrinsics *K, int32_t n);
 int sne_estimate_batched(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int grad,
                          int agg, int out_type, void *stream);
 
+/* For callers that cannot allocate memory during the call (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * sne_estimate_batched with the same kernels and bitwise the same results,
+ * but the descriptor table and the tile queues live in a fixed device array
+ * of the library (one per GPU, about 0.4 MB, held until the process ends)
+ * and are staged through pinned memory the context set up when it was
+ * created.  The call itself allocates nothing: no hipMalloc, hipFree or
+ * pinned-memory allocation.  At most SNE_NOALLOC_MAX_FRAMES frames
+ * (SNE_ERR_BUDGET beyond; nothing is launched then).  The array is shared
+ * by every call on the GPU and keeps the last call's contents: calls that
+ * overlap on one GPU (on different streams, or from contexts on several
+ * threads) race, and their results are undefined; calls in order on one
+ * stream are safe.  A call waits until the previous call's table copy on
+ * this context has left the staging.  Other arguments and errors as for
+ * sne_estimate_batched. */
+#define SNE_NOALLOC_MAX_FRAMES 4096
+int sne_estimate_batched_noalloc(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind,
+                                 int grad, int agg, int out_type, void *stream);
+
 /* Tile shape: each group of `lanes` lanes of a wavefront covers
  * `cols_per_lane * lanes` columns by `rows` rows of a frame.  cols_per_lane is
  * 1, 2 or 4 (vector width of the loads and stores); rows is 1..1024; lanes is

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <vector>
 
 
@@ -287,26 +288,13 @@ int ensure_slot(Slot &s, size_t n) {
     return SNE_OK;
 }
 
-int batched_impl(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int grad, int agg,
-                 int out_type, void *stream, const TileChoice *force) {
-    if (!ctx || n < 0 || !valid_enum(kind, grad, agg, out_type)) return SNE_ERR_ARG;
-    if (n == 0) return SNE_OK;  // an empty batch: frames may be NULL
-    if (!frames) return SNE_ERR_ARG;
-    int pxmax = 4, maxH = 0, maxW = 0;
-    const int rc0 = scan_batch(ctx, frames, n, kind, out_type, maxH, maxW, pxmax);
-    if (rc0 != SNE_OK) return rc0;
-    Variant v{kind, grad, agg, out_type, 1};
-    TileChoice t = force ? *force : pick_tile(ctx, maxH, maxW, n, v, pxmax, true);
-    if (t.px > pxmax || t.rows < 1) return SNE_ERR_ARG;
-    v.px = kernel_px(t);
-    Slot &s = ctx->slots[ctx->next_slot];
-    ctx->next_slot = (ctx->next_slot + 1) % kSlots;
-    if (hipSetDevice(ctx->device) != hipSuccess) return SNE_ERR_HIP;
-    int rc = ensure_slot(s, (size_t)n);
-    if (rc != SNE_OK) return rc;
-    if (s.used && hipEventSynchronize(s.done) != hipSuccess) return SNE_ERR_HIP;
-
-    const BatchTable bt = batch_table(s.h_stage, n);
+// Fill the host staging `stage` with the batch's table (frames, tile prefix
+// sums, zeroed queue heads), copy it to `d_table` on `st` and launch the
+// persistent kernel on it.  The frames were validated by scan_batch.
+int stage_and_launch(sne_ctx *ctx, const sne_frame *frames, int32_t n, const Variant &v,
+                     const TileChoice &t, int grad, void *stage, void *d_table, hipStream_t st,
+                     hipEvent_t copied) {
+    const BatchTable bt = batch_table(stage, n);
     int64_t tiles = 0;
     for (int32_t i = 0; i < n; ++i) {
         const sne_frame &f = frames[i];
@@ -325,13 +313,13 @@ int batched_impl(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int
     *bt.head = BatchHeader{};
     bt.head->nframes = n;
     bt.head->ntiles = (int32_t)tiles;
-    hipStream_t st = (hipStream_t)stream;
     // one copy of the used part of the table; it also zeroes the tile queues
-    if (hipMemcpyAsync(s.d_table, s.h_stage, batch_table_bytes(n), hipMemcpyHostToDevice, st) !=
+    if (hipMemcpyAsync(d_table, stage, batch_table_bytes(n), hipMemcpyHostToDevice, st) !=
         hipSuccess)
         return SNE_ERR_HIP;
+    if (copied && hipEventRecord(copied, st) != hipSuccess) return SNE_ERR_HIP;
     BatchArgs a;
-    a.table = s.d_table;
+    a.table = d_table;
     a.ktable = reinterpret_cast<const float4 *>(ctx->d_K);
     a.rows = t.rows;
     a.chunk = 1;
@@ -340,7 +328,30 @@ int batched_impl(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int
     hipError_t e = batch_grid(ctx, v, tiles, a.chunk, &grid);
     if (e != hipSuccess) return SNE_ERR_HIP;
     e = launch_batch(v, a, grid, st);
-    if (e != hipSuccess) return SNE_ERR_HIP;
+    return e == hipSuccess ? SNE_OK : SNE_ERR_HIP;
+}
+
+int batched_impl(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int grad, int agg,
+                 int out_type, void *stream, const TileChoice *force) {
+    if (!ctx || n < 0 || !valid_enum(kind, grad, agg, out_type)) return SNE_ERR_ARG;
+    if (n == 0) return SNE_OK;  // an empty batch: frames may be NULL
+    if (!frames) return SNE_ERR_ARG;
+    int pxmax = 4, maxH = 0, maxW = 0;
+    const int rc0 = scan_batch(ctx, frames, n, kind, out_type, maxH, maxW, pxmax);
+    if (rc0 != SNE_OK) return rc0;
+    Variant v{kind, grad, agg, out_type, 1};
+    TileChoice t = force ? *force : pick_tile(ctx, maxH, maxW, n, v, pxmax, true);
+    if (t.px > pxmax || t.rows < 1) return SNE_ERR_ARG;
+    v.px = kernel_px(t);
+    Slot &s = ctx->slots[ctx->next_slot];
+    ctx->next_slot = (ctx->next_slot + 1) % kSlots;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SNE_ERR_HIP;
+    int rc = ensure_slot(s, (size_t)n);
+    if (rc != SNE_OK) return rc;
+    if (s.used && hipEventSynchronize(s.done) != hipSuccess) return SNE_ERR_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    rc = stage_and_launch(ctx, frames, n, v, t, grad, s.h_stage, s.d_table, st, nullptr);
+    if (rc != SNE_OK) return rc;
     if (hipEventRecord(s.done, st) != hipSuccess) return SNE_ERR_HIP;
     s.used = true;
     return SNE_OK;
@@ -447,6 +458,34 @@ void report_tile(const TileChoice &t, sne_tile *tile) {
 }  // namespace
 }  // namespace sne
 
+// Descriptor table and tile queues of sne_estimate_batched_noalloc: one
+// fixed device array per GPU, held until the process ends, instead of memory
+// allocated per context.  Host code never uses the array's name as an
+// address: each device's copy is looked up once (with that device current)
+// when a context is created on it, and that pointer is what the kernels get.
+static __device__ __align__(256) unsigned char
+    scratch[sne::batch_table_bytes(SNE_NOALLOC_MAX_FRAMES)];
+
+namespace sne {
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch_ptr;  // per device, filled at context creation
+
+// Device address of `scratch` on `device`, which must be current.
+int scratch_address(int device, void **out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize(device + 1, nullptr);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SNE_ERR_HIP;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return SNE_OK;
+}
+}  // namespace
+}  // namespace sne
+
 using namespace sne;
 
 extern "C" {
@@ -481,6 +520,14 @@ int sne_ctx_create(sne_ctx **out, int device) {
         c->num_cu = prop.multiProcessorCount;
         c->arch = prop.gcnArchName;
     }
+    // everything sne_estimate_batched_noalloc needs besides the device array
+    if (scratch_address(device, &c->noalloc_table) != SNE_OK ||
+        hipHostMalloc(&c->noalloc_stage, batch_table_bytes(SNE_NOALLOC_MAX_FRAMES),
+                      hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&c->noalloc_copied, hipEventDisableTiming) != hipSuccess) {
+        (void)sne_ctx_destroy(c);
+        return SNE_ERR_HIP;
+    }
     *out = c;
     return SNE_OK;
 }
@@ -501,6 +548,11 @@ int sne_ctx_destroy(sne_ctx *ctx) {
         (void)hipEventDestroy(ctx->eval_done);
     }
     if (ctx->d_eval) (void)hipFree(ctx->d_eval);
+    if (ctx->noalloc_copied) {
+        (void)hipEventSynchronize(ctx->noalloc_copied);
+        (void)hipEventDestroy(ctx->noalloc_copied);
+    }
+    if (ctx->noalloc_stage) (void)hipHostFree(ctx->noalloc_stage);
     delete ctx;
     return SNE_OK;
 }
@@ -548,6 +600,28 @@ int sne_set_intrinsics_table(sne_ctx *ctx, const sne_intrinsics *K, int32_t n) {
 int sne_estimate_batched(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int grad,
                          int agg, int out_type, void *stream) {
     return batched_impl(ctx, frames, n, kind, grad, agg, out_type, stream, nullptr);
+}
+
+int sne_estimate_batched_noalloc(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind,
+                                 int grad, int agg, int out_type, void *stream) {
+    if (!ctx || n < 0 || !valid_enum(kind, grad, agg, out_type)) return SNE_ERR_ARG;
+    if (n == 0) return SNE_OK;
+    if (!frames) return SNE_ERR_ARG;
+    if (n > SNE_NOALLOC_MAX_FRAMES) return SNE_ERR_BUDGET;
+    if (!ctx->noalloc_table || !ctx->noalloc_stage || !ctx->noalloc_copied) return SNE_ERR_STATE;
+    int pxmax = 4, maxH = 0, maxW = 0;
+    const int rc0 = scan_batch(ctx, frames, n, kind, out_type, maxH, maxW, pxmax);
+    if (rc0 != SNE_OK) return rc0;
+    Variant v{kind, grad, agg, out_type, 1};
+    const TileChoice t = pick_tile(ctx, maxH, maxW, n, v, pxmax, true);
+    if (t.px > pxmax || t.rows < 1) return SNE_ERR_ARG;
+    v.px = kernel_px(t);
+    if (hipSetDevice(ctx->device) != hipSuccess) return SNE_ERR_HIP;
+    // the previous call's copy out of the staging must be done before it is
+    // rewritten (an event never recorded counts as complete)
+    if (hipEventSynchronize(ctx->noalloc_copied) != hipSuccess) return SNE_ERR_HIP;
+    return stage_and_launch(ctx, frames, n, v, t, grad, ctx->noalloc_stage, ctx->noalloc_table,
+                            (hipStream_t)stream, ctx->noalloc_copied);
 }
 
 int sne_set_tile(sne_ctx *ctx, const sne_tile *tile) {
@@ -685,9 +759,9 @@ int sne_autotune_save(const sne_ctx *ctx, const char *path) {
     for (const auto &kv : ctx->cache) {
         const TileKey &k = kv.first;
         const TileChoice &t = kv.second;
-        std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d %d %d\n", ctx->arch.c_str(), kVersion,
-                     k.H, k.W, k.bclass, k.kind, k.grad, k.agg, k.out, t.px, t.rows, t.remap,
-                     t.half);
+        std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d %d %d\n", ctx->arch.c_str(),
+                     kTileCacheVersion, k.H, k.W, k.bclass, k.kind, k.grad, k.agg, k.out, t.px,
+                     t.rows, t.remap, t.half);
     }
     const bool ok = std::fclose(f) == 0;
     return ok ? SNE_OK : SNE_ERR_IO;
@@ -706,7 +780,7 @@ int sne_autotune_load(sne_ctx *ctx, const char *path) {
                                     &H, &W, &bc, &kind, &grad, &agg, &out, &px, &rows, &remap,
                                     &half);
         if (got != 12 && got != 13) continue;
-        if (ctx->arch != arch || ver != kVersion) continue;
+        if (ctx->arch != arch || ver != kTileCacheVersion) continue;
         if (!valid_enum(kind, grad, agg, out) || !(px == 1 || px == 2 || px == 4) || rows < 1 ||
             rows > 1024 || bc < 0 || bc > kUnevenClass)
             continue;

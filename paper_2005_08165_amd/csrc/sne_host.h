@@ -16,7 +16,10 @@
 
 namespace sne {
 
-constexpr int kVersion = 10100;  // 1.1.0
+constexpr int kVersion = 10200;  // 1.2.0
+// Tile-shape cache entries carry the version of the kernels they were timed
+// on; it changes only when the kernels' speed characteristics do.
+constexpr int kTileCacheVersion = 10100;
 constexpr int kSlots = 4;        // in-flight uneven batches per context
 constexpr int kEvalMaxPhis = 8;  // thresholds of sne_accuracy
 constexpr int kEvalRow = 2 + kEvalMaxPhis;  // per-block partials: sum psi, count, hits
@@ -120,6 +123,12 @@ struct sne_ctx {
     // last call, which a call on another stream waits for before reusing them
     double *d_eval = nullptr;
     hipEvent_t eval_done = nullptr;
+    // sne_estimate_batched_noalloc: this device's copy of the library's
+    // fixed table array, pinned staging for it and the event of the last
+    // call's copy out of the staging (all set up when the context is created)
+    void *noalloc_table = nullptr;
+    void *noalloc_stage = nullptr;
+    hipEvent_t noalloc_copied = nullptr;
 };
 
 namespace sne {

@@ -23,6 +23,10 @@ TUNING_TABLE = os.path.join(PKG, "tuning.txt")  # written by paper_2005_08165_am
 HEADER = os.path.join(os.path.dirname(PKG), "include", "sne.h")
 
 SNE_OK = 0
+SNE_ERR_ARG, SNE_ERR_BUDGET, SNE_ERR_STATE = -1, -3, -5
+SNE_NOALLOC_MAX_FRAMES = 4096  # include/sne.h
+# version tag the library writes into (and requires of) tile-table entries
+TILE_CACHE_VERSION = 10100
 STATUS = {0: "SNE_OK", -1: "SNE_ERR_ARG", -2: "SNE_ERR_UNSUPPORTED", -3: "SNE_ERR_BUDGET",
           -4: "SNE_ERR_HIP", -5: "SNE_ERR_STATE", -6: "SNE_ERR_FULL", -7: "SNE_ERR_IO"}
 
@@ -130,6 +134,8 @@ _SIGS = {
     "sne_set_intrinsics_table": ([_vp, ctypes.POINTER(Intrinsics), _i32], _int),
     "sne_estimate_batched": ([_vp, ctypes.POINTER(FrameDesc), _i32, _int, _int, _int, _int, _vp],
                              _int),
+    "sne_estimate_batched_noalloc": ([_vp, ctypes.POINTER(FrameDesc), _i32, _int, _int, _int,
+                                      _int, _vp], _int),
     "sne_set_tile": ([_vp, ctypes.POINTER(Tile)], _int),
     "sne_get_tile": ([_vp, _i32, _i32, _i32, _int, _int, _int, _int, ctypes.POINTER(Tile)], _int),
     "sne_autotune": ([_vp, _i32, _i32, _i32, _int, _int, _int, _int, ctypes.POINTER(Tile)], _int),

@@ -17,8 +17,24 @@ def test_exports_every_declared_function():
     assert set(sne._SIGS) <= set(names)
 
 
+def test_header_constants_match_binding():
+    import re
+    text = open(sne.HEADER).read()
+    m = re.search(r"#define SNE_NOALLOC_MAX_FRAMES (\d+)", text)
+    assert m and int(m.group(1)) == sne.SNE_NOALLOC_MAX_FRAMES
+    for name in ("SNE_ERR_ARG", "SNE_ERR_BUDGET", "SNE_ERR_STATE"):
+        m = re.search(r"#define %s \((-\d+)\)" % name, text)
+        assert m and int(m.group(1)) == getattr(sne, name), name
+
+
+def test_noalloc_rejects_bad_arguments_before_the_gpu():
+    L = sne.lib()
+    # a NULL context is refused first, whatever else is passed
+    assert L.sne_estimate_batched_noalloc(None, None, 1, 1, 0, 0, 1, None) == sne.SNE_ERR_ARG
+
+
 def test_version_and_status_strings():
-    assert sne.version() == 10100
+    assert sne.version() == 10200
     assert sne.status_string(0) == "ok"
     assert sne.status_string(-1) == "invalid argument"
     assert sne.status_string(12345) == "unknown status"
@@ -115,12 +131,14 @@ def test_shipped_tuning_table_is_well_formed():
         assert len(f) == 13, line
         arch, ver, H, W, bc, kind, grad, agg, out, px, rows, remap, half = (
             [f[0]] + [int(x) for x in f[1:]])
-        assert ver == sne.version() and H >= 1 and W >= 1 and bc in (0, 1, 2, 3)
+        assert ver == sne.TILE_CACHE_VERSION and H >= 1 and W >= 1 and bc in (0, 1, 2, 3)
         assert kind in sne.KIND.values() and grad in sne.GRAD.values()
         assert agg in sne.AGG.values() and out in (0, 1)
         assert px in (1, 2, 4) and 1 <= rows <= 1024 and remap in (0, 1) and half in (0, 1)
         keys.add((H, W, bc, kind, grad, agg, out))
     assert (480, 640, 2, 0, 1, 1, 0) in keys
+    src = open(os.path.join(os.path.dirname(sne.LIB_PATH), "csrc", "sne_host.h")).read()
+    assert "kTileCacheVersion = %d;" % sne.TILE_CACHE_VERSION in src
 
 
 def test_frames_past_the_32bit_offset_limits_are_rejected():
