@@ -104,11 +104,73 @@ def plain_single_frame(torch, S, sne, grad, agg, reps=200):
     lat.sort()
     wall, ev = time_launches(torch, one, 20, reps)
     px = 480 * 640
+    gbs = px * 17 * reps / ev / 1e9
     return {"variant": "%s-%s" % (grad, agg), "mpix_per_s": round(px * reps / ev / 1e6, 1),
             "frames_per_s": round(reps / ev, 1),
+            "roofline": {"bound": "latency", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                         "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                         "note": "17 B/px algorithmic; the 5.2 MB frame stays in the 256 MB "
+                                 "last-level cache across launches, so this is not an HBM rate"},
             "us_per_frame_back_to_back": round(ev / reps * 1e6, 2),
             "latency_us_p50": round(lat[len(lat) // 2] * 1e6, 1),
             "latency_us_p99": round(lat[int(len(lat) * 0.99) - 1] * 1e6, 1)}
+
+
+def disparity_batch(torch, S, sne, reps=300, warmup=30):
+    """The stereo workload: one launch over 128 FP32 disparity frames of
+    375x1242 (road plane and box obstacles, f = 721.5 px, 0.54 m baseline,
+    1-128 px disparity, +-0.25 px uniform noise, 0 outside that range),
+    Scharr gradients, median, FP32 normals + mask (17 B/px, 1.01 GB per
+    launch, four times the last-level cache)."""
+    B = 128
+    cam = S.ROAD_CAM
+    raw = torch.stack([S.make_road(2000 + i, cam, device="cuda").raw for i in range(B)])
+    H, W = cam.H, cam.W
+    nrm = torch.empty((B, 3, H, W), device="cuda")
+    msk = torch.empty((B, H, W), dtype=torch.uint8, device="cuda")
+    ctx = sne.Context(0)
+    K = cam.as_tuple()
+    tile = ctx.get_tile(H, W, B, "disparity_f32", "scharr", "median", "f32")
+
+    def step(i):
+        sne.estimate_uniform(raw, K, "disparity_f32", "scharr", "median", normals=nrm, mask=msk,
+                             ctx=ctx)
+
+    torch.cuda.synchronize()
+    wall, ev = time_launches(torch, step, warmup, reps)
+    px = B * H * W
+    gbs = px * 17 * reps / ev / 1e9
+    return {"workload": "batch128_375x1242_f32disparity_scharr_median", "frames": B,
+            "mpix": round(px / 1e6, 2), "us_per_launch": round(ev / reps * 1e6, 2),
+            "mpix_per_s": round(px * reps / ev / 1e6, 1),
+            "frames_per_s": round(B * reps / ev, 1),
+            "tile": {"cols_per_lane": tile[0], "rows": tile[1], "lanes": tile[2]},
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                         "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                         "algorithmic_bytes_per_launch": px * 17}}
+
+
+def probe_calibration(torch, sne, px=4 * 64 * 480 * 640, reps=20):
+    """Rates the GPU's memory sustains for streaming patterns with none of
+    the method's arithmetic (hand-written HIP kernels, nontemporal stores):
+    read-only, write-only, copy, and the stencil's own streams (4 B in,
+    three 4 B planes + 1 B mask out per pixel).  Over 4 x 64 frames of
+    480x640 (1.34 GB for the stencil pattern), so nothing stays in cache."""
+    src = torch.empty(px, device="cuda").uniform_(0.5, 5.0)
+    dst = torch.empty(3 * px, device="cuda")
+    msk = torch.empty(px, dtype=torch.uint8, device="cuda")
+    cases = [("read", px * 4, lambda i: sne.bandwidth_probe("read", src, dst)),
+             ("write", 3 * px * 4, lambda i: sne.bandwidth_probe("write", None, dst)),
+             ("copy", 2 * px * 4, lambda i: sne.bandwidth_probe("copy", src, dst[:px])),
+             ("stencil_pattern", px * 17, lambda i: sne.bandwidth_probe("stencil", src, dst, msk))]
+    out = {}
+    for name, nbytes, fn in cases:
+        wall, ev = time_launches(torch, fn, 3, reps)
+        gbs = nbytes * reps / ev / 1e9
+        out[name] = {"bytes": nbytes, "us": round(ev / reps * 1e6, 1), "GBs": round(gbs, 1),
+                     "frac_of_peak": round(gbs / PEAK_HBM_GBS, 4)}
+    del src, dst, msk
+    return out
 
 
 def copy_calibration(torch, nbytes=1 << 30, reps=10):
@@ -293,6 +355,59 @@ def cpu_baseline(host_batch, K, grad, agg, min_s=10.0, budget_s=20.0):
             "single_thread_sample": "%d frames, 1 thread, %.1f s" % (one, dt1)}
 
 
+def oracle_rate(frames, kind, Ks, grad, agg, tc, threads, min_s):
+    """Pixels per second of the FP64 oracle over whole passes of `frames`
+    (host arrays with intrinsics Ks), at least min_s seconds; stops at a
+    frame boundary once min_s has passed."""
+    import numpy as np
+    import oracle
+    K32 = [tuple(float(np.float32(x)) for x in K) for K in Ks]
+    done_px = done = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < min_s:
+        for i, f in enumerate(frames):
+            oracle.estimate(f, kind, K32[i], grad, agg, tc=tc, threads=threads)
+            done_px += f.size
+            done += 1
+            if time.perf_counter() - t0 >= min_s:
+                break
+    dt = time.perf_counter() - t0
+    return done_px / dt, done, dt
+
+
+def cpu_baselines_other(S, threads, min_all=3.0, min_one=2.0):
+    """The oracle on the host for the single-frame, stereo and uneven-batch
+    workloads, with all cores and with one thread (bounded samples: the
+    frames named in each `sample`, passed over repeatedly for at least the
+    stated time)."""
+    import numpy as np
+    legs = []
+    fr = S.make_indoor(0)
+    legs.append(("single_480x640_f32depth_fd_mean", [fr.raw.numpy()], "depth_f32",
+                 [fr.cam.as_tuple()], "fd", "mean", 1.0, "1 frame 480x640 (indoor scene 0)"))
+    road = [S.make_road(2000 + i).raw.numpy() for i in range(4)]
+    legs.append(("batch128_375x1242_f32disparity_scharr_median", road, "disparity_f32",
+                 [S.ROAD_CAM.as_tuple()] * 4, "scharr", "median", S.ROAD_BASELINE,
+                 "frames 0-3 of the 128-frame batch"))
+    shapes, Ks, ki, frames = S.uneven_batch(64, seed=3999, scenes_per_shape=2)
+    u16 = [f.numpy() for f in frames]
+    for agg in ("mean", "median"):
+        legs.append(("uneven1024_u16_fd_%s" % agg, u16, "depth_u16", [Ks[k] for k in ki], "fd",
+                     agg, 1.0, "the first 64 frames of the uneven batch's size draw "
+                     "(%.1f Mpx)" % (sum(h * w for h, w in shapes) / 1e6)))
+    out = {}
+    for name, fs, kind, Kl, grad, agg, tc, sample in legs:
+        log("cpu baseline", name)
+        r_all, n_all, t_all = oracle_rate(fs, kind, Kl, grad, agg, tc, threads, min_all)
+        r_one, n_one, t_one = oracle_rate(fs, kind, Kl, grad, agg, tc, 1, min_one)
+        out[name] = {"value": round(r_all / 1e6, 2), "unit": "Mpix/s", "cores": threads,
+                     "kind": "oracle",
+                     "sample": "%s; %d frames in %.1f s" % (sample, n_all, t_all),
+                     "single_thread_value": round(r_one / 1e6, 2),
+                     "single_thread_sample": "%d frames, 1 thread, %.1f s" % (n_one, t_one)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -309,6 +424,8 @@ def main():
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-disparity", action="store_true")
+    ap.add_argument("--disparity-steps", type=int, default=300)
     ap.add_argument("--serving-rate", type=float, default=0.0,
                     help="run the serving loop at this one offered rate (FD-mean) only")
     ap.add_argument("--autotune", action="store_true",
@@ -390,10 +507,15 @@ def main():
     }
     log("copy calibration")
     res["copy_calibration"] = copy_calibration(torch)
+    log("streaming-pattern calibration (hand-written probes)")
+    res["probe_calibration"] = probe_calibration(torch, sne)
     if not args.no_plain:
         log("plain single-frame launches")
         res["plain_single_frame"] = [plain_single_frame(torch, S, sne, args.grad, args.agg),
                                      plain_single_frame(torch, S, sne, "fd", "mean")]
+    if not args.no_disparity:
+        log("disparity batch (128 x 375x1242)")
+        res["disparity_batch"] = disparity_batch(torch, S, sne, reps=args.disparity_steps)
     if not args.no_uneven:
         log("uneven persistent batch")
         res["uneven_batch"] = [uneven_batch(torch, S, sne, "mean", autotune=args.autotune),
@@ -412,6 +534,7 @@ def main():
         log("cpu baseline (oracle)")
         host = bufs[0][0].cpu().numpy()
         res["cpu_baseline"] = cpu_baseline(host, K, args.grad, args.agg)
+        res["cpu_baselines_other"] = cpu_baselines_other(S, res["cpu_baseline"]["cores"])
     print(json.dumps(res), flush=True)
 
 

@@ -362,6 +362,28 @@ typedef struct {
 } sne_sim_config;
 int sne_sched_simulate(const sne_sim_config *cfg, sne_server_stats *st);
 
+/* Bandwidth calibration, a measurement aid beside the method: streaming
+ * kernels that move the bytes of an access pattern with none of the method's
+ * arithmetic, so that the rate the GPU's memory sustains for each pattern can
+ * be set beside the stencil's own.  One launch on `stream`; n is a count of
+ * 4-byte elements, a multiple of 4; src and dst 16-byte aligned device
+ * pointers, mask 4-byte aligned.
+ *   SNE_PROBE_READ     reads n floats of src; writes one float per 1024
+ *                      elements (rounded up) to dst, to keep the loads live.
+ *   SNE_PROBE_WRITE    writes n floats to dst (src unused, may be NULL).
+ *   SNE_PROBE_COPY     dst[i] = src[i] for n floats.
+ *   SNE_PROBE_STENCIL  the stencil's per-pixel streams for n pixels: reads
+ *                      n floats of src, writes three planes of n floats to
+ *                      dst (dst[c * n + i]) and n bytes to mask.
+ * Stores are nontemporal, as the stencil's output stores are.  SNE_ERR_ARG
+ * on a bad mode, n, pointer or alignment. */
+#define SNE_PROBE_READ 0
+#define SNE_PROBE_WRITE 1
+#define SNE_PROBE_COPY 2
+#define SNE_PROBE_STENCIL 3
+int sne_bandwidth_probe(int mode, const void *src, void *dst, uint8_t *mask, int64_t n,
+                        void *stream);
+
 /* Human-readable name of a status code (static string). */
 const char *sne_status_string(int status);
 

@@ -43,6 +43,7 @@ def _units():
     units.append((os.path.join(CSRC, "sne_api.hip"), os.path.join(OBJ, "sne_api.o"), []))
     units.append((os.path.join(CSRC, "sne_server.hip"), os.path.join(OBJ, "sne_server.o"), []))
     units.append((os.path.join(CSRC, "sne_eval.hip"), os.path.join(OBJ, "sne_eval.o"), []))
+    units.append((os.path.join(CSRC, "sne_calib.hip"), os.path.join(OBJ, "sne_calib.o"), []))
     units.append((os.path.join(CSRC, "sne_sched.cpp"), os.path.join(OBJ, "sne_sched.o"), []))
     return units
 

@@ -156,6 +156,7 @@ _SIGS = {
     "sne_server_destroy": ([_vp], _int),
     "sne_server_run_open_loop": ([_vp, ctypes.POINTER(LoadgenConfig), ctypes.POINTER(ServerStats)],
                                  _int),
+    "sne_bandwidth_probe": ([_int, _vp, _vp, _vp, _i64, _vp], _int),
     "sne_sched_simulate": ([ctypes.POINTER(SimConfig), ctypes.POINTER(ServerStats)], _int),
 }
 
@@ -612,3 +613,20 @@ def status_string(code: int) -> str:
 
 def version() -> int:
     return lib().sne_version()
+
+
+PROBE = {"read": 0, "write": 1, "copy": 2, "stencil": 3}
+
+
+def bandwidth_probe(mode: str, src: Optional[torch.Tensor], dst: torch.Tensor,
+                    mask: Optional[torch.Tensor] = None, n: Optional[int] = None,
+                    stream=None) -> None:
+    """sne_bandwidth_probe: one streaming launch of a calibration pattern
+    over n float elements (default: all of src, or of dst for "write")."""
+    _on_gpu(src, dst, mask)
+    if n is None:
+        n = (dst if src is None else src).numel()
+    check("sne_bandwidth_probe",
+          lib().sne_bandwidth_probe(_enum(PROBE, mode, "mode"), _ptr(src), dst.data_ptr(),
+                                    _ptr(mask), int(n), _stream(stream)))
+

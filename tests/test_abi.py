@@ -199,3 +199,12 @@ def test_binding_rejects_host_tensors():
         sne.estimate(raw, (8.0, 8.0, 3.5, 3.5), "depth_f32")
     with pytest.raises(ValueError, match="on the GPU"):
         sne.estimate_uniform(raw[None], (8.0, 8.0, 3.5, 3.5), "depth_f32")
+
+
+@pytest.mark.parametrize("mode,n,src,dst,mask", [
+    (9, 16, FAKE, FAKE, FAKE), (-1, 16, FAKE, FAKE, FAKE), (2, 6, FAKE, FAKE, FAKE),
+    (2, -4, FAKE, FAKE, FAKE), (2, 16, None, FAKE, None), (1, 16, None, None, None),
+    (2, 16, FAKE + 4, FAKE, None), (3, 16, FAKE, FAKE, None), (3, 16, FAKE, FAKE, FAKE + 1),
+])
+def test_bandwidth_probe_argument_errors(mode, n, src, dst, mask):
+    assert sne.lib().sne_bandwidth_probe(mode, src, dst, mask, n, None) == sne.SNE_ERR_ARG
