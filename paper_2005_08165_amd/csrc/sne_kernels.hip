@@ -353,7 +353,15 @@ template <> struct Out<OUT_F32> {
 };
 template <> struct Out<OUT_F16> {
     using T = _Float16;
-    __device__ static T cvt(float x) { return (_Float16)x; }  // round to nearest even
+    // Round the FP32 value to nearest even.  The value is pinned first so
+    // that the compiler cannot fold the product that feeds it into a mixed-
+    // precision multiply rounded once to FP16: whether it did would depend
+    // on the kernel it inlines into, and the same pixel could then round
+    // differently alone and in a batch.
+    __device__ static T cvt(float x) {
+        asm("" : "+v"(x));
+        return (_Float16)x;
+    }
 };
 
 template <int PX> struct MaskWord;
@@ -394,41 +402,38 @@ __device__ __forceinline__ void candidates(const float (&Nj)[8], const float (&r
 
 // Median of the kept candidates; zj/zc decide which slots are left out.
 // `general` pads left-out slots alternately +inf / -inf; otherwise all 8
-// are kept.  *none: nothing kept.
+// are kept.  With nothing kept, the four +inf and four -inf pads give
+// -inf + inf = NaN, which the caller's norm test turns into the degenerate
+// normal.
 template <int KIND>
 __device__ __forceinline__ float median8(const float (&Nj)[8], const float (&rj)[8],
-                                         const float (&zj)[8], float zc, bool general,
-                                         bool &none) {
+                                         const float (&zj)[8], float zc, bool general) {
     float t[8];
     if (!general) {
-        none = false;
         candidates<KIND>(Nj, rj, zc, t);
         return median_pair(t, false);
     }
     candidates<KIND>(Nj, rj, zc, t);
     float pad = kInf;
-    bool all = true;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const bool drop = zj[j] == zc;
         t[j] = drop ? pad : t[j];
         pad = drop ? -pad : pad;
-        all = all && drop;
     }
-    none = all;
     return median_pair(t, pad < 0.f);  // odd number left out -> position 3
 }
 
 // Mean of the kept candidates.  Both paths add in the same tree order and
 // 1/8 is exact, so a pixel with nothing left out gets the same bits whichever
-// path its wavefront takes.
+// path its wavefront takes.  With nothing kept the sum is +0 and 0 * (1/0)
+// is NaN, which the caller's norm test turns into the degenerate normal.
 template <int KIND>
 __device__ __forceinline__ float mean8(const float (&Nj)[8], const float (&rj)[8],
-                                       const float (&zj)[8], float zc, bool general, bool &none) {
+                                       const float (&zj)[8], float zc, bool general) {
     float t[8];
     candidates<KIND>(Nj, rj, zc, t);
     if (!general) {
-        none = false;
         const float s = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
         return s * 0.125f;
     }
@@ -439,10 +444,17 @@ __device__ __forceinline__ float mean8(const float (&Nj)[8], const float (&rj)[8
         t[j] = drop ? 0.f : t[j];
         m += drop ? 0 : 1;
     }
-    none = (m == 0);
     const float s = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
-    return s * (m == 8 ? 0.125f : rcp((float)m));
+    return s * rcp((float)m);  // v_rcp_f32 returns 1/8 exactly for m = 8
 }
+
+// Integer raw values (uint16) repeat along iso-depth lines so often that
+// nearly every wavefront holds a pixel with a left-out neighbour: those
+// kinds take the general aggregation everywhere, without the per-pixel test
+// and wavefront vote that let the other kinds skip it.  With no branch the
+// compiler also shares a pair's equality test between the two pixels of the
+// pair.
+template <int KIND> constexpr bool kTieHeavy = KIND == KIND_U16;
 
 // Outputs are written once and not read back by this kernel: nontemporal
 // stores keep them from displacing the input rows that neighbouring tiles
@@ -527,16 +539,19 @@ __device__ __forceinline__ void tile_row(const FrameDesc &f, const InBuf &ib, in
         // this wavefront needs it (the choice is wave-uniform, and both paths
         // give the same result when nothing is left out).
         // (signs do not matter here: the raw pair values are used)
-        const float rmax = vmax8abs(rc.rE[c], rc.rE[c - 1], pd.rS[k], pu.rS[k], pd.rSE[c],
-                                    pu.rSE[k], pd.rSW[k], pu.rSW[c]);
-        const bool any_drop = !(rmax < kInf);
-        const bool general = __builtin_amdgcn_ballot_w64(valid && any_drop) != 0;
-        bool none;
-        const float phi = (AGG == AGG_MEAN) ? mean8<KIND>(Nj, rj, zj, zc, general, none)
-                                            : median8<KIND>(Nj, rj, zj, zc, general, none);
+        bool general = true;
+        if constexpr (!kTieHeavy<KIND>) {
+            const float rmax = vmax8abs(rc.rE[c], rc.rE[c - 1], pd.rS[k], pu.rS[k], pd.rSE[c],
+                                        pu.rSE[k], pd.rSW[k], pu.rSW[c]);
+            const bool any_drop = !(rmax < kInf);
+            general = __builtin_amdgcn_ballot_w64(valid && any_drop) != 0;
+        }
+        const float phi = (AGG == AGG_MEAN) ? mean8<KIND>(Nj, rj, zj, zc, general)
+                                            : median8<KIND>(Nj, rj, zj, zc, general);
         const float nx = f.fx * Gu, ny = f.fy * Gv, nz = B + phi;
         const float n2 = fmaf(nx, nx, fmaf(ny, ny, nz * nz));
-        const bool deg = none || !(n2 > 0.f);
+        // nothing kept (phi NaN) or a zero vector: the degenerate normal
+        const bool deg = !(n2 > 0.f);
         const float inv = __builtin_amdgcn_rsqf(n2);
         const bool keep = valid && !deg;
         ox.v[k] = Out<OUT>::cvt(keep ? -nx * inv : 0.f);
