@@ -30,6 +30,7 @@ KIND_DTYPE = {"depth_f32": np.float32, "depth_u16": np.uint16, "depth_f16": np.f
               "disparity_f64": np.float64}
 GRADS = {"fd": 0, "sobel": 1, "scharr": 2, "prewitt": 3}
 AGGS = {"mean": 0, "median": 1}
+RULES = {"strict": 0, "lenient": 1}
 
 _lib = None
 
@@ -53,7 +54,7 @@ def _load():
         dp = ctypes.POINTER(ctypes.c_double)
         common = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
                   ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                  ctypes.c_double, ctypes.c_int, ctypes.c_int]
+                  ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         lib.orc_estimate.argtypes = common + [dp, ctypes.c_void_p, dp, ctypes.c_void_p,
                                               ctypes.c_int]
         lib.orc_estimate.restype = ctypes.c_int
@@ -83,8 +84,12 @@ def _prep(raw: np.ndarray, kind: str) -> np.ndarray:
 
 def estimate(raw: np.ndarray, kind: str, K: Sequence[float], grad: str = "fd",
              agg: str = "mean", tc: float = 1.0, threads: int = 0, unnorm: bool = False,
-             mcount: bool = False):
+             mcount: bool = False, rule: str = "strict"):
     """Normals [3,H,W] float64 and mask [H,W] uint8 of one image.
+
+    ``rule``: "strict" (a fully valid 3x3 window at an interior pixel) or
+    "lenient" (valid neighbours only, one-sided gradient lines; see the header
+    of sne_oracle.c).
 
     K = (fx, fy, u0, v0) as the values the caller wants used (pass the FP32
     values a GPU run used to compare like with like).  With ``unnorm`` the
@@ -98,7 +103,8 @@ def estimate(raw: np.ndarray, kind: str, K: Sequence[float], grad: str = "fd",
     un = np.zeros((3, H, W), np.float64) if unnorm else None
     mc = np.zeros((H, W), np.int32) if mcount else None
     rc = _load().orc_estimate(raw.ctypes.data, KINDS[kind], H, W, W, fx, fy, u0, v0, float(tc),
-                              GRADS[grad], AGGS[agg], _dp(nrm), msk.ctypes.data, _dp(un),
+                              GRADS[grad], AGGS[agg], RULES[rule], _dp(nrm), msk.ctypes.data,
+                              _dp(un),
                               None if mc is None else mc.ctypes.data, int(threads))
     if rc != 0:
         raise ValueError("oracle rejected its arguments (rc=%d)" % rc)
@@ -112,7 +118,7 @@ def estimate(raw: np.ndarray, kind: str, K: Sequence[float], grad: str = "fd",
 
 def estimate_pixels(raw: np.ndarray, kind: str, K: Sequence[float], pix: np.ndarray,
                     grad: str = "fd", agg: str = "mean", tc: float = 1.0, threads: int = 0,
-                    unnorm: bool = False, mcount: bool = False):
+                    unnorm: bool = False, mcount: bool = False, rule: str = "strict"):
     """Normals [n,3] and mask [n] at flat pixel indices ``pix`` (v*W + u)."""
     raw = _prep(raw, kind)
     H, W = raw.shape
@@ -124,7 +130,8 @@ def estimate_pixels(raw: np.ndarray, kind: str, K: Sequence[float], pix: np.ndar
     un = np.zeros((n, 3), np.float64) if unnorm else None
     mc = np.zeros(n, np.int32) if mcount else None
     rc = _load().orc_estimate_pixels(raw.ctypes.data, KINDS[kind], H, W, W, fx, fy, u0, v0,
-                                     float(tc), GRADS[grad], AGGS[agg], pix.ctypes.data, n,
+                                     float(tc), GRADS[grad], AGGS[agg], RULES[rule],
+                                     pix.ctypes.data, n,
                                      _dp(nrm), msk.ctypes.data, _dp(un),
                                      None if mc is None else mc.ctypes.data, int(threads))
     if rc != 0:

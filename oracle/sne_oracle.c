@@ -52,6 +52,27 @@
  * Raw kinds: FP32 depth, uint16 depth (any unit, read as an integer), FP16
  * depth, FP32 disparity, and - for the exactness tests only - FP64 depth and
  * FP64 disparity.
+ *
+ * Lenient rule (rule = 1).  The paper's Q_i is "the neighbours of p_i"
+ * (Sec. II, eq. planesvd) and its evaluation data have holes (Sec. IV-A),
+ * but it does not say what a hole does to the three filters.  This reading
+ * keeps every pixel that can still be estimated:
+ *   - Samples outside the frame are invalid; Q_i is the set of VALID
+ *     8-neighbours, and candidates come from those whose raw value differs
+ *     from that of p (steps 7-8 unchanged).
+ *   - Each line of a gradient filter with a non-zero weight w (a row of
+ *     K_x = w [-1 0 1], a column of K_y) contributes w (s_+ - s_-) when both
+ *     outer samples are valid, else the one-sided 2 w (s_+ - s_0) or
+ *     2 w (s_0 - s_-) when the line's middle sample and one outer sample are
+ *     valid (all three agree on an affine s), else nothing.  The sum over the
+ *     available lines is scaled by (sum of all line weights) / (sum of the
+ *     available line weights), so that it estimates the same multiple of the
+ *     derivative as the full filter.
+ *   - mask = 1 iff p is valid and both gradients have at least one line;
+ *     border pixels included.
+ *   - A pixel whose valid neighbours all carry its raw value gets (0, 0, -1).
+ * On a window whose 9 samples are valid this is the strict definition (up to
+ * the order of the additions in the gradient lines).
  */
 #include <math.h>
 #include <stddef.h>
@@ -83,7 +104,7 @@ typedef struct {
     int kind, H, W;
     int64_t pitch;               /* elements between rows */
     double fx, fy, u0, v0, tc;
-    int grad, agg;
+    int grad, agg, rule;
 } orc_img;
 
 /* IEEE binary16 -> double, from the format's definition. */
@@ -219,6 +240,148 @@ static void pixel(const orc_img *im, int v, int u, double out[3], unsigned char 
     out[2] = -nz / norm;
 }
 
+/* One line of a gradient filter under the lenient rule: samples sm (minus
+ * side), s0 (middle), sp (plus side) with validity flags.  Returns 1 and the
+ * line's difference in *L (without the weight), or 0 if the line has too few
+ * valid samples. */
+static int lenient_line(int okm, int ok0, int okp, double sm, double s0, double sp, double *L) {
+    if (okm && okp) {
+        *L = sp - sm;
+        return 1;
+    }
+    if (ok0 && okp) {
+        *L = 2.0 * (sp - s0);
+        return 1;
+    }
+    if (ok0 && okm) {
+        *L = 2.0 * (s0 - sm);
+        return 1;
+    }
+    return 0;
+}
+
+/* The pixel under the lenient rule (see the header); same outputs as pixel(). */
+static void pixel_lenient(const orc_img *im, int v, int u, double out[3], unsigned char *mask,
+                          double unnorm[3], int *m_out) {
+    out[0] = out[1] = out[2] = 0.0;
+    if (unnorm) unnorm[0] = unnorm[1] = unnorm[2] = 0.0;
+    *mask = 0;
+    *m_out = -1;
+
+    double raw[3][3], z[3][3], s[3][3];
+    int ok[3][3];
+    const int disp = is_disparity(im->kind);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            const int vv = v + a - 1, uu = u + b - 1;
+            raw[a][b] = 0.0;
+            ok[a][b] = 0;
+            if (vv >= 0 && vv < im->H && uu >= 0 && uu < im->W) {
+                raw[a][b] = raw_at(im, vv, uu);
+                ok[a][b] = isfinite(raw[a][b]) && raw[a][b] > 0.0;
+            }
+            z[a][b] = s[a][b] = 0.0;
+            if (ok[a][b]) {
+                z[a][b] = disp ? im->fx * im->tc / raw[a][b] : raw[a][b];
+                s[a][b] = disp ? raw[a][b] : 1.0 / z[a][b];
+            }
+        }
+    if (!ok[1][1]) return;
+
+    /* Filters 1 and 2 over the available lines.  Row a of K_x is
+     * K[a][2] * [-1 0 1]; column b of K_y = K_x^T is K[b][2] * [-1 0 1]^T. */
+    const double (*K)[3] = KX[im->grad];
+    double Gu = 0.0, Gv = 0.0, wu_all = 0.0, wu = 0.0, wv_all = 0.0, wv = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double w = K[a][2];
+        if (w == 0.0) continue;
+        double L;
+        wu_all += w;
+        if (lenient_line(ok[a][0], ok[a][1], ok[a][2], s[a][0], s[a][1], s[a][2], &L)) {
+            Gu += w * L;
+            wu += w;
+        }
+    }
+    for (int b = 0; b < 3; ++b) {
+        const double w = K[b][2];
+        if (w == 0.0) continue;
+        double L;
+        wv_all += w;
+        if (lenient_line(ok[0][b], ok[1][b], ok[2][b], s[0][b], s[1][b], s[2][b], &L)) {
+            Gv += w * L;
+            wv += w;
+        }
+    }
+    if (wu == 0.0 || wv == 0.0) return;
+    Gu *= wu_all / wu;
+    Gv *= wv_all / wv;
+    *mask = 1;
+
+    int all_equal = 1;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            if (ok[a][b] && raw[a][b] != raw[1][1]) all_equal = 0;
+    if (all_equal) {
+        out[2] = -1.0;
+        *m_out = 0;
+        return;
+    }
+
+    const double nx = disp ? Gu : im->fx * Gu;
+    const double ny = disp ? Gv : im->fy * Gv;
+    double P[3][3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            const double uq = (double)(u + b - 1), vq = (double)(v + a - 1);
+            P[a][b][0] = z[a][b] * (uq - im->u0) / im->fx;
+            P[a][b][1] = z[a][b] * (vq - im->v0) / im->fy;
+            P[a][b][2] = z[a][b];
+        }
+    double c[8];
+    int m = 0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            if (a == 1 && b == 1) continue;
+            if (!ok[a][b] || raw[a][b] == raw[1][1]) continue;  /* not in Q_i, or dZ = 0 */
+            const double dX = P[a][b][0] - P[1][1][0];
+            const double dY = P[a][b][1] - P[1][1][1];
+            const double dZ = P[a][b][2] - P[1][1][2];
+            c[m++] = (dX * nx + dY * ny) / dZ;
+        }
+    *m_out = m;
+    double phi;
+    if (im->agg == A_MEAN) {
+        double sum = 0.0;
+        for (int j = 0; j < m; ++j) sum += c[j];
+        phi = sum / m;
+    } else {
+        qsort(c, (size_t)m, sizeof(double), cmp_double);
+        phi = (m % 2) ? c[m / 2] : 0.5 * (c[m / 2 - 1] + c[m / 2]);
+    }
+    const double nz = -phi;
+    if (unnorm) {
+        unnorm[0] = nx;
+        unnorm[1] = ny;
+        unnorm[2] = nz;
+    }
+    const double norm = sqrt(nx * nx + ny * ny + nz * nz);
+    if (norm == 0.0) {
+        out[2] = -1.0;
+        return;
+    }
+    out[0] = -nx / norm;
+    out[1] = -ny / norm;
+    out[2] = -nz / norm;
+}
+
+static void eval_pixel(const orc_img *im, int v, int u, double out[3], unsigned char *mask,
+                       double unnorm[3], int *m_out) {
+    if (im->rule)
+        pixel_lenient(im, v, u, out, mask, unnorm, m_out);
+    else
+        pixel(im, v, u, out, mask, unnorm, m_out);
+}
+
 static int check_args(const void *raw, int kind, int H, int W, int64_t pitch, double fx,
                       double fy, int grad, int agg) {
     if (!raw || H < 1 || W < 1 || pitch < W) return ORC_EARG;
@@ -233,11 +396,12 @@ static int check_args(const void *raw, int kind, int H, int W, int64_t pitch, do
  * unnorm: optional [3][H][W]; mcount: optional [H][W] int (candidates kept,
  * -1 masked).  nthreads <= 0 uses the OpenMP default. */
 int orc_estimate(const void *raw, int kind, int H, int W, int64_t pitch, double fx, double fy,
-                 double u0, double v0, double tc, int grad, int agg, double *normals,
+                 double u0, double v0, double tc, int grad, int agg, int rule, double *normals,
                  unsigned char *mask, double *unnorm, int *mcount, int nthreads) {
-    if (check_args(raw, kind, H, W, pitch, fx, fy, grad, agg) != ORC_OK || !normals || !mask)
+    if (check_args(raw, kind, H, W, pitch, fx, fy, grad, agg) != ORC_OK || !normals || !mask ||
+        (rule != 0 && rule != 1))
         return ORC_EARG;
-    orc_img im = {raw, kind, H, W, pitch, fx, fy, u0, v0, tc, grad, agg};
+    orc_img im = {raw, kind, H, W, pitch, fx, fy, u0, v0, tc, grad, agg, rule};
     const int64_t plane = (int64_t)H * W;
 #ifdef _OPENMP
     if (nthreads <= 0) nthreads = omp_get_max_threads();
@@ -248,7 +412,7 @@ int orc_estimate(const void *raw, int kind, int H, int W, int64_t pitch, double 
             double n[3], un[3];
             unsigned char mk;
             int m;
-            pixel(&im, v, u, n, &mk, un, &m);
+            eval_pixel(&im, v, u, n, &mk, un, &m);
             const int64_t i = (int64_t)v * W + u;
             normals[i] = n[0];
             normals[plane + i] = n[1];
@@ -267,15 +431,15 @@ int orc_estimate(const void *raw, int kind, int H, int W, int64_t pitch, double 
 /* Selected pixels only (flat indices v*W + u).  normals: [n][3]; mask: [n];
  * unnorm optional [n][3]; mcount optional [n]. */
 int orc_estimate_pixels(const void *raw, int kind, int H, int W, int64_t pitch, double fx,
-                        double fy, double u0, double v0, double tc, int grad, int agg,
+                        double fy, double u0, double v0, double tc, int grad, int agg, int rule,
                         const int64_t *pix, int64_t n, double *normals, unsigned char *mask,
                         double *unnorm, int *mcount, int nthreads) {
     if (check_args(raw, kind, H, W, pitch, fx, fy, grad, agg) != ORC_OK || !pix || !normals ||
-        !mask || n < 0)
+        !mask || n < 0 || (rule != 0 && rule != 1))
         return ORC_EARG;
     for (int64_t k = 0; k < n; ++k)
         if (pix[k] < 0 || pix[k] >= (int64_t)H * W) return ORC_EARG;
-    orc_img im = {raw, kind, H, W, pitch, fx, fy, u0, v0, tc, grad, agg};
+    orc_img im = {raw, kind, H, W, pitch, fx, fy, u0, v0, tc, grad, agg, rule};
 #ifdef _OPENMP
     if (nthreads <= 0) nthreads = omp_get_max_threads();
 #pragma omp parallel for schedule(static) num_threads(nthreads)
@@ -284,7 +448,7 @@ int orc_estimate_pixels(const void *raw, int kind, int H, int W, int64_t pitch, 
         double nn[3], un[3];
         unsigned char mk;
         int m;
-        pixel(&im, (int)(pix[k] / W), (int)(pix[k] % W), nn, &mk, un, &m);
+        eval_pixel(&im, (int)(pix[k] / W), (int)(pix[k] % W), nn, &mk, un, &m);
         normals[3 * k] = nn[0];
         normals[3 * k + 1] = nn[1];
         normals[3 * k + 2] = nn[2];

@@ -339,9 +339,10 @@ def test_golden_worked_examples():
         K = list(ex["K"])
         K[2] += 1.0
         K[3] += 1.0                             # keep u - u0, v - v0 unchanged
+        rule = ex.get("rule", "strict")
         for agg in ex["aggs"]:
             nrm, msk, un, mc = oracle.estimate(img, ex["kind"], K, ex["grad"], agg,
-                                               tc=ex["tc"], unnorm=True, mcount=True)
+                                               tc=ex["tc"], unnorm=True, mcount=True, rule=rule)
             assert msk[2, 2] == 1
             assert mc[2, 2] == ex["m"]
             np.testing.assert_allclose(nrm[:, 2, 2], ex["normal"][agg], atol=1e-14)
@@ -349,7 +350,8 @@ def test_golden_worked_examples():
                 np.testing.assert_allclose(un[:, 2, 2], ex["nprime"][agg], rtol=1e-14, atol=1e-15)
             # the exact brute force reproduces the hand derivation too
             xm, xn, xv = exact.pixel(win.astype(int).tolist(), 1, 1, ex["K"], ex["grad"], agg,
-                                     disparity=ex["kind"].startswith("disparity"), tc=1)
+                                     disparity=ex["kind"].startswith("disparity"), tc=1,
+                                     rule=rule)
             assert xm == 1
             np.testing.assert_allclose(xv, ex["normal"][agg], atol=1e-14)
 
@@ -467,3 +469,137 @@ def test_accuracy_metrics_agree_with_the_atan2_angle_and_frame_axes():
     psi = np.stack([oracle.angular_error_deg(v[b], g[b]) for b in range(2)])[mask != 0]
     assert m == int(mask.sum())
     assert abs(eA - psi.mean()) < 1e-9 and eP == [float(np.mean(psi <= 45.0))]
+
+
+# --------------------------------------------------------------------------
+# lenient rule: holes and borders (valid neighbours only, one-sided lines)
+# --------------------------------------------------------------------------
+
+def _holes(shape, frac, seed):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(size=shape) < frac
+
+
+@pytest.mark.parametrize("grad", GRADS)
+@pytest.mark.parametrize("agg", AGGS)
+def test_lenient_planes_exact_with_holes_and_borders(grad, agg):
+    """Inverse depth (or disparity) is affine on a plane, so the one-sided
+    line differences equal the central ones and the rescaled filter equals
+    the full one: every pixel the lenient rule keeps, border pixels and
+    pixels next to holes included, gets the exact plane normal and
+    n'.p = KSCALE (t_c KSCALE for disparity)."""
+    H, W = 30, 44
+    for kind, K, tc in [("depth_f64", (52.0, 50.0, 21.5, 14.5), 1.0),
+                        ("disparity_f64", (52.0, 52.0, 21.5, 14.5), 0.54)]:
+        for i, (n, b) in enumerate(_random_planes(31, 3, H, W, K)):
+            z = _plane_depth(n, b, H, W, K)
+            holes = _holes(z.shape, 0.2, 40 + i)
+            raw = np.where(holes, 0.0, z if kind == "depth_f64" else tc * K[0] / z)
+            nrm, msk, un = oracle.estimate(raw, kind, K, grad, agg, tc=tc, unnorm=True,
+                                           rule="lenient")
+            m = msk.astype(bool)
+            strict = oracle.estimate(raw, kind, K, grad, agg, tc=tc)[1].astype(bool)
+            assert (m >= strict).all() and m.sum() > strict.sum() + W  # borders and holes
+            assert m[0].any() and m[:, -1].any()
+            assert not m[holes].any()
+            err = oracle.angular_error_deg(nrm, np.broadcast_to(n[:, None, None], nrm.shape))[m]
+            assert err.max() < 1e-8, (kind, err.max())
+            dot = (un * _backproject(z, K)).sum(0)[m]
+            np.testing.assert_allclose(dot, KSCALE[grad] * tc, rtol=1e-9)
+
+
+@pytest.mark.parametrize("grad", GRADS)
+@pytest.mark.parametrize("agg", AGGS)
+def test_lenient_equals_strict_on_full_windows(grad, agg):
+    """Where the whole 3x3 window is valid the lenient rule is the strict
+    definition; elsewhere it keeps pixels the strict rule masks."""
+    fr = S.make_cluttered(77, S.Camera(60, 80, 60.2, 60.2, 39.5, 29.5), holes=0.05)
+    raw = fr.raw.numpy()
+    K = fr.cam.as_tuple()
+    n_s, m_s = oracle.estimate(raw, "depth_f32", K, grad, agg)
+    n_l, m_l = oracle.estimate(raw, "depth_f32", K, grad, agg, rule="lenient")
+    ms = m_s.astype(bool)
+    assert (m_l[ms] == 1).all() and m_l.sum() > 1.1 * m_s.sum()
+    err = oracle.angular_error_deg(n_l[:, ms], n_s[:, ms])
+    assert err.max() < 1e-9
+    assert (n_l[:, ~m_l.astype(bool)] == 0).all()
+
+
+def _tiny_hole_images(seed, count, lo=1, hi=6, H=6, W=7):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        img = rng.integers(lo, hi, size=(H, W))
+        img[rng.uniform(size=(H, W)) < 0.25] = 0
+        out.append(img)
+    return out
+
+
+@pytest.mark.parametrize("grad", GRADS)
+@pytest.mark.parametrize("agg", AGGS)
+def test_lenient_bruteforce_exact(grad, agg):
+    """The C oracle under the lenient rule against the independent rational
+    brute force, on small integer images with holes (every pixel, borders
+    included): same mask, normals to 1e-12, n' to 1e-12 relative."""
+    K = (2.5, 3.0, 3.5, 2.75)
+    for img in _tiny_hole_images(300 + GRADS.index(grad), 4):
+        mask_x, npr_x, nrm_x = exact.image(img.tolist(), K, grad, agg, rule="lenient")
+        nrm, msk, un = oracle.estimate(img.astype(np.uint16), "depth_u16", K, grad, agg,
+                                       unnorm=True, rule="lenient")
+        assert (np.array(mask_x) == msk).all()
+        np.testing.assert_allclose(nrm, np.moveaxis(np.array(nrm_x), -1, 0), atol=1e-12)
+        H, W = img.shape
+        for v in range(H):
+            for u in range(W):
+                if npr_x[v][u] is not None:
+                    ref = np.array([float(x) for x in npr_x[v][u]])
+                    np.testing.assert_allclose(un[:, v, u], ref,
+                                               atol=1e-12 * max(np.linalg.norm(ref), 1e-300))
+
+
+def test_lenient_bruteforce_exact_disparity():
+    K = (3.0, 3.0, 3.5, 2.5)
+    for agg in AGGS:
+        for img in _tiny_hole_images(400, 3, lo=1, hi=9):
+            mask_x, _, nrm_x = exact.image(img.tolist(), K, "scharr", agg, disparity=True, tc=1,
+                                           rule="lenient")
+            nrm, msk = oracle.estimate(img.astype(np.float32), "disparity_f32", K, "scharr", agg,
+                                       rule="lenient")
+            assert (np.array(mask_x) == msk).all()
+            np.testing.assert_allclose(nrm, np.moveaxis(np.array(nrm_x), -1, 0), atol=1e-12)
+
+
+def test_lenient_mask_rules():
+    """Hand cases of the lenient mask: a valid pixel is kept iff each
+    gradient has a line with its middle sample and one outer sample valid
+    (or both outer samples)."""
+    K = (5.0, 5.0, 2.0, 2.0)
+    img = np.full((5, 5), 3, dtype=np.uint16)
+
+    def mask_at(a, grad, v=2, u=2):
+        return oracle.estimate(a, "depth_u16", K, grad, "mean", rule="lenient")[1][v, u]
+
+    # isolated valid pixel: no line has two valid samples
+    iso = np.zeros_like(img)
+    iso[2, 2] = 3
+    assert mask_at(iso, "fd") == 0 and mask_at(iso, "sobel") == 0
+    # FD: both horizontal neighbours missing -> no G_u; one missing -> kept
+    a = img.copy()
+    a[2, 1] = a[2, 3] = 0
+    assert mask_at(a, "fd") == 0
+    # Sobel and Prewitt still have the rows above and below
+    assert mask_at(a, "sobel") == 1 and mask_at(a, "prewitt") == 1
+    a[2, 3] = 3
+    assert mask_at(a, "fd") == 1
+    # a row whose middle sample is missing still works from its two ends
+    b = img.copy()
+    b[1, 2] = 0
+    assert mask_at(b, "fd") == 1
+    # an invalid pixel is never kept; corners of a full image are
+    c = img.copy()
+    c[2, 2] = 0
+    assert mask_at(c, "sobel") == 0
+    assert mask_at(img, "fd", 0, 0) == 1 and mask_at(img, "scharr", 4, 4) == 1
+    # constant image: every kept pixel is degenerate
+    n, m = oracle.estimate(img, "depth_u16", K, "sobel", "median", rule="lenient")
+    assert m.all() and (n[2] == -1).all() and (n[:2] == 0).all()
