@@ -425,6 +425,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-disparity", action="store_true")
+    ap.add_argument("--no-lenient", action="store_true")
     ap.add_argument("--disparity-steps", type=int, default=300)
     ap.add_argument("--serving-rate", type=float, default=0.0,
                     help="run the serving loop at this one offered rate (FD-mean) only")
@@ -505,6 +506,26 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_per_launch,
                      "kernel_us": round(ev / args.steps * 1e6, 2)},
     }
+    if not args.no_lenient:
+        log("lenient rule on the same batches")
+
+        def step_len(i):
+            raw, nrm, msk = bufs[i % NBUF]
+            sne.estimate_uniform(raw, K, "depth_f32+lenient", args.grad, args.agg, normals=nrm,
+                                 mask=msk, ctx=ctx)
+
+        lsteps = max(args.steps // 3, 10)
+        wall_l, ev_l = time_launches(torch, step_len, max(args.warmup // 3, 5), lsteps)
+        gbs = bytes_per_launch / (ev_l / lsteps) / 1e9
+        res["lenient_batch"] = {
+            "workload": workload + "_lenient",
+            "note": "holes and borders under the lenient rule: a gradient line falls back to a "
+                    "one-sided difference, invalid neighbours leave filter 3",
+            "us_per_launch": round(ev_l / lsteps * 1e6, 2),
+            "mpix_per_s": round(px * lsteps / ev_l / 1e6, 1),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                         "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                         "algorithmic_bytes_per_launch": bytes_per_launch}}
     log("copy calibration")
     res["copy_calibration"] = copy_calibration(torch)
     log("streaming-pattern calibration (hand-written probes)")

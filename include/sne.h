@@ -72,6 +72,21 @@ typedef struct {
 #define SNE_DEPTH_F16 2      /* IEEE binary16 depth                         */
 #define SNE_DISPARITY_F32 3  /* float disparity in pixels                   */
 
+/* Holes and the frame border: OR SNE_LENIENT into any kind to estimate
+ * every pixel that still can be, instead of only those with a fully valid
+ * 3x3 window.  The paper's Q_i is the set of neighbours of p (Sec. II, eq.
+ * planesvd) and its evaluation data have holes (Sec. IV-A), but it does not
+ * say how a hole affects the filters; under this rule samples outside the
+ * frame are invalid, Q_i holds the VALID neighbours, and each gradient line
+ * (a row of K_x, a column of K_y) uses its two outer samples, else its middle
+ * sample and one outer sample at twice the one-sided difference, else drops
+ * out, the available lines being rescaled to the full filter's weight.  The
+ * mask is 1 iff the pixel is valid and each gradient has a line (border
+ * pixels included); a pixel whose valid neighbours all carry its raw value
+ * gets (0, 0, -1).  Where the whole window is valid the result is bitwise
+ * that of the strict rule. */
+#define SNE_LENIENT 0x100
+
 /* Gradient filters 1 and 2 (Sec. IV-B): K_x below, K_y = K_x^T, applied as a
  * correlation.  FD is [-1 0 1]; Sobel rows [-1 0 1; -2 0 2; -1 0 1]; Scharr
  * [-3 0 3; -10 0 10; -3 0 3]; Prewitt three rows of [-1 0 1]. */

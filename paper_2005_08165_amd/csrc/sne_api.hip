@@ -17,7 +17,9 @@
 namespace sne {
 
 bool valid_enum(int kind, int grad, int agg, int out) {
-    return kind >= SNE_DEPTH_F32 && kind <= SNE_DISPARITY_F32 && grad >= SNE_GRAD_FD &&
+    const int base = base_kind(kind);
+    return (kind & ~(SNE_LENIENT | 0xff)) == 0 && base >= SNE_DEPTH_F32 &&
+           base <= SNE_DISPARITY_F32 && grad >= SNE_GRAD_FD &&
            grad <= SNE_GRAD_PREWITT && agg >= SNE_AGG_MEAN && agg <= SNE_AGG_MEDIAN &&
            out >= SNE_OUT_F32 && out <= SNE_OUT_F16;
 }
@@ -28,7 +30,7 @@ bool valid_K(const sne_intrinsics *K, int kind) {
           std::isfinite(K->v0)))
         return false;
     if (!(K->fx > 0.f && K->fy > 0.f)) return false;
-    if (kind == SNE_DISPARITY_F32 && K->fx != K->fy) return false;
+    if (base_kind(kind) == SNE_DISPARITY_F32 && K->fx != K->fy) return false;
     return true;
 }
 
@@ -37,20 +39,30 @@ bool valid_K_row(const sne_ctx *ctx, int32_t k, int kind) {
     return valid_K(&ctx->h_K[k], kind);
 }
 
-size_t in_elem(int kind) { return kind == SNE_DEPTH_F32 || kind == SNE_DISPARITY_F32 ? 4 : 2; }
+size_t in_elem(int kind) {
+    return base_kind(kind) == SNE_DEPTH_F32 || base_kind(kind) == SNE_DISPARITY_F32 ? 4 : 2;
+}
 size_t out_elem(int out) { return out == SNE_OUT_F32 ? 4 : 2; }
 
 // 3-row kernels as the ratio side / centre of their central-difference
 // weights (the kernels' scale cancels from the normal): Sobel 1:2, Scharr
-// 3:10, Prewitt 1:1.  FD uses the centre row only.
-void grad_weights(int grad, float &wa, float &wb) {
+// 3:10, Prewitt 1:1.  FD uses the centre row only.  The lenient rule's
+// rescaling factors are the full weight 1 + 2 wa over the available weight
+// (1 + wa, 1, 2 wa, wa), rounded once from double.
+void grad_weights(int grad, GradW &w) {
+    double a = 0.0;
     switch (grad) {
-    case SNE_GRAD_SOBEL: wa = 0.5f; break;
-    case SNE_GRAD_SCHARR: wa = 0.3f; break;
-    case SNE_GRAD_PREWITT: wa = 1.f; break;
-    default: wa = 0.f; break;
+    case SNE_GRAD_SOBEL: a = 0.5; break;
+    case SNE_GRAD_SCHARR: a = 0.3; break;
+    case SNE_GRAD_PREWITT: a = 1.0; break;
+    default: break;
     }
-    wb = 1.f;
+    w.wa = (float)a;
+    const double full = 1.0 + 2.0 * a;
+    w.r[0] = (float)(full / (1.0 + a));
+    w.r[1] = (float)full;
+    w.r[2] = a > 0.0 ? (float)(full / (2.0 * a)) : 0.f;
+    w.r[3] = a > 0.0 ? (float)(full / a) : 0.f;
 }
 
 bool aligned(const void *p, size_t bytes) { return ((uintptr_t)p % bytes) == 0; }
@@ -105,21 +117,24 @@ TileChoice pick_tile(const sne_ctx *ctx, int H, int W, int64_t B, const Variant 
     }
     if (ctx) {
         // an uneven batch prefers a shape tuned on the persistent kernel
-        for (int bc : {uneven ? kUnevenClass : -1, batch_class(B)}) {
-            if (bc < 0) continue;
-            auto it = ctx->cache.find(TileKey{H, W, bc, v.kind, v.grad, v.agg, v.out});
-            if (it != ctx->cache.end()) {
-                TileChoice t = it->second;
-                while (t.px > pxmax) t.px >>= 1;
-                return t;
+        // a shape tuned for the variant itself, else (lenient rule) the one
+        // tuned for the strict rule of the same variant
+        for (int kind : {v.kind, base_kind(v.kind)})
+            for (int bc : {uneven ? kUnevenClass : -1, batch_class(B)}) {
+                if (bc < 0) continue;
+                auto it = ctx->cache.find(TileKey{H, W, bc, kind, v.grad, v.agg, v.out});
+                if (it != ctx->cache.end()) {
+                    TileChoice t = it->second;
+                    while (t.px > pxmax) t.px >>= 1;
+                    return t;
+                }
             }
-        }
     }
     return default_tile(ctx, H, W, B, pxmax);
 }
 
 hipError_t launch_uniform(const Variant &v, const UniformArgs &a, int grid, hipStream_t s) {
-    switch (v.kind) {
+    switch (base_kind(v.kind)) {
     case SNE_DEPTH_F32: return launch_uniform_f32(v, a, grid, s);
     case SNE_DEPTH_U16: return launch_uniform_u16(v, a, grid, s);
     case SNE_DEPTH_F16: return launch_uniform_f16(v, a, grid, s);
@@ -128,7 +143,7 @@ hipError_t launch_uniform(const Variant &v, const UniformArgs &a, int grid, hipS
 }
 
 hipError_t launch_batch(const Variant &v, const BatchArgs &a, int grid, hipStream_t s) {
-    switch (v.kind) {
+    switch (base_kind(v.kind)) {
     case SNE_DEPTH_F32: return launch_batch_f32(v, a, grid, s);
     case SNE_DEPTH_U16: return launch_batch_u16(v, a, grid, s);
     case SNE_DEPTH_F16: return launch_batch_f16(v, a, grid, s);
@@ -137,7 +152,7 @@ hipError_t launch_batch(const Variant &v, const BatchArgs &a, int grid, hipStrea
 }
 
 hipError_t occupancy_batch(const Variant &v, int *blocks) {
-    switch (v.kind) {
+    switch (base_kind(v.kind)) {
     case SNE_DEPTH_F32: return occupancy_batch_f32(v, blocks);
     case SNE_DEPTH_U16: return occupancy_batch_u16(v, blocks);
     case SNE_DEPTH_F16: return occupancy_batch_f16(v, blocks);
@@ -149,8 +164,10 @@ hipError_t batch_grid(sne_ctx *ctx, const Variant &v, int64_t tiles, int chunk, 
     // one instantiation per (kind, FD or 3-row filter, agg, out, px class);
     // a fixed table, so that no call after the first allocates anything
     const int pxi = (v.px % 100 == 4 ? 2 : v.px % 100 == 2 ? 1 : 0) + (v.px >= 100 ? 3 : 0);
+    const int len = (v.kind & SNE_LENIENT) ? 1 : 0;
     const int key =
-        (((v.kind * 2 + (v.grad == SNE_GRAD_FD ? 0 : 1)) * 2 + v.agg) * 2 + v.out) * 6 + pxi;
+        ((((base_kind(v.kind) * 2 + (v.grad == SNE_GRAD_FD ? 0 : 1)) * 2 + v.agg) * 2 + v.out) *
+             2 + len) * 6 + pxi;
     if (key < 0 || key >= kOccEntries) return hipErrorInvalidValue;
     int per_cu = ctx->occ[key].load(std::memory_order_relaxed);
     if (per_cu == 0) {
@@ -251,7 +268,7 @@ int uniform_impl(sne_ctx *ctx, const void *in, int32_t B, int32_t H, int32_t W, 
     if (ntiles > INT32_MAX - 4 * kWavesPerBlock) return SNE_ERR_BUDGET;
     a.ntiles = (int32_t)ntiles;
     a.xcd_remap = t.remap;
-    grad_weights(grad, a.wa, a.wb);
+    grad_weights(grad, a.gw);
     const int grid = (int)((ntiles + kWavesPerBlock - 1) / kWavesPerBlock);
     if (ctx && hipSetDevice(ctx->device) != hipSuccess) return SNE_ERR_HIP;
     hipError_t e = launch_uniform(v, a, grid, (hipStream_t)stream);
@@ -323,7 +340,7 @@ int stage_and_launch(sne_ctx *ctx, const sne_frame *frames, int32_t n, const Var
     a.ktable = reinterpret_cast<const float4 *>(ctx->d_K);
     a.rows = t.rows;
     a.chunk = 1;
-    grad_weights(grad, a.wa, a.wb);
+    grad_weights(grad, a.gw);
     int grid = 0;
     hipError_t e = batch_grid(ctx, v, tiles, a.chunk, &grid);
     if (e != hipSuccess) return SNE_ERR_HIP;
@@ -682,12 +699,13 @@ int sne_autotune(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int gr
         const int threads = 256;
         const int64_t nfill = nset * npx;
         const int blocks = (int)((nfill + threads - 1) / threads);
-        if (kind == SNE_DEPTH_F32 || kind == SNE_DISPARITY_F32)
+        const int base = base_kind(kind);
+        if (base == SNE_DEPTH_F32 || base == SNE_DISPARITY_F32)
             hipLaunchKernelGGL(fill_pattern<float>, dim3(blocks), dim3(threads), 0, st,
-                               (float *)in, nfill, W, kind);
+                               (float *)in, nfill, W, base);
         else
             hipLaunchKernelGGL(fill_pattern<uint16_t>, dim3(blocks), dim3(threads), 0, st,
-                               (uint16_t *)in, nfill, W, kind);
+                               (uint16_t *)in, nfill, W, base);
         sne_intrinsics K{(float)W, (float)W, (W - 1) * 0.5f, (H - 1) * 0.5f};
         const int pxmax = max_px(in, out, mask, W, W, W, W, (int64_t)H * W, 3LL * H * W,
                                  (int64_t)H * W, (int64_t)H * W, kind, out_type);

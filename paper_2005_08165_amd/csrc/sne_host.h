@@ -29,8 +29,9 @@ constexpr int kEvalRow = 2 + kEvalMaxPhis;  // per-block partials: sum psi, coun
 constexpr int kUnevenClass = 3;
 
 // Persistent-kernel instantiations: 4 kinds x {FD, 3-row} x 2 agg x 2 out x
-// 6 column classes (1, 2, 4 columns per lane, full or half wave).
-constexpr int kOccEntries = 4 * 2 * 2 * 2 * 6;
+// 2 rules x 6 column classes (1, 2, 4 columns per lane, full or half wave).
+constexpr int kOccEntries = 4 * 2 * 2 * 2 * 2 * 6;
+static_assert(kLenientFlag == SNE_LENIENT, "kernel-side flag mirrors the ABI");
 
 struct TileKey {
     int H, W, bclass, kind, grad, agg, out;
@@ -79,7 +80,7 @@ inline bool frame_fits(int64_t H, int64_t in_pitch, int kind, int64_t out_pitch,
            H * mask_pitch <= (int64_t)UINT32_MAX;
 }
 
-void grad_weights(int grad, float &wa, float &wb);
+void grad_weights(int grad, GradW &w);
 int max_px(const void *in, const void *out, const uint8_t *mask, int W, int64_t in_pitch,
            int64_t out_pitch, int64_t mask_pitch, int64_t in_fs, int64_t out_fs, int64_t mask_fs,
            int64_t out_plane, int kind, int out_type);

@@ -24,6 +24,16 @@ struct FrameDesc {
     int32_t pad_;
 };
 
+// Gradient-filter weights as the kernels use them: a 3-row filter divided by
+// its centre weight (wa = side / centre; FD uses the centre line only), and
+// for the lenient rule the factors that rescale a sum of the available lines
+// to the full filter's weight 1 + 2 wa: r[0] the centre and one side line,
+// r[1] the centre line only, r[2] both side lines, r[3] one side line.
+struct GradW {
+    float wa;
+    float r[4];
+};
+
 // Uniform batch: frame b = frame 0 shifted by b * stride.
 struct UniformArgs {
     FrameDesc f;
@@ -32,7 +42,7 @@ struct UniformArgs {
     int32_t nstrips, nbands, rows;  // tile grid of one frame
     int32_t ntiles;                 // B * nbands * nstrips
     int32_t xcd_remap;              // 1: give each XCD a contiguous tile range
-    float wa, wb;                   // 3-row filters: wa = side / centre weight; wb unused (1)
+    GradW gw;
 };
 
 // Uneven batch.  Its tables are one block of device memory that the host
@@ -86,12 +96,12 @@ struct BatchArgs {
     void *table;          // the block above, queue heads 0 at launch
     const float4 *ktable; // device-resident intrinsics (fx, fy, u0, v0)
     int32_t rows, chunk;
-    float wa, wb;
+    GradW gw;
 };
 
 // Variant selector used by the host dispatcher.
 struct Variant {
-    int kind;   // SNE_DEPTH_F32 ...
+    int kind;   // SNE_DEPTH_F32 ..., possibly with SNE_LENIENT
     int grad;   // SNE_GRAD_*
     int agg;    // SNE_AGG_*
     int out;    // SNE_OUT_*
@@ -116,6 +126,8 @@ hipError_t occupancy_batch_disp(const Variant &v, int *blocks);
 
 // Kernel-side enum values (mirror include/sne.h).
 enum { KIND_F32 = 0, KIND_U16 = 1, KIND_F16 = 2, KIND_DISP = 3 };
+constexpr int kLenientFlag = 0x100;  // ORed into a kind: the lenient rule
+inline constexpr int base_kind(int kind) { return kind & ~kLenientFlag; }
 enum { AGG_MEAN = 0, AGG_MEDIAN = 1 };
 enum { OUT_F32 = 0, OUT_F16 = 1 };
 

@@ -37,6 +37,14 @@
 //   whatever their number m; odd m takes position 3.
 //   Output: (-f_x G_u, -f_y G_v, B + Phi) / norm, the camera-facing unit
 //   normal; m = 0 or a zero vector gives (0, 0, -1); masked pixels +0.
+//
+// Lenient rule (LEN): a wavefront holding a valid pixel whose window is not
+// fully valid (a hole nearby, or the frame border, which loads as 0) forms
+// each gradient line from its two outer samples, else from its middle and one
+// outer sample at twice the one-sided difference, rescales the available
+// lines to the filter's full weight, and leaves invalid neighbours out of
+// filter 3.  The mask is then: valid centre and a line for each gradient.  On
+// a full window every step is the strict one, bit for bit.
 #include "sne_internal.h"
 
 #ifndef SNE_KIND
@@ -60,8 +68,11 @@
 #ifndef SNE_BATCH_WAVES_PER_EU
 #define SNE_BATCH_WAVES_PER_EU 4
 #endif
+// The lenient rule's extra line arithmetic does not fit that budget without
+// spilling: its instantiations get the compiler's choice.
 #if SNE_BATCH_WAVES_PER_EU > 0
-#define SNE_BATCH_OCCUPANCY __attribute__((amdgpu_waves_per_eu(SNE_BATCH_WAVES_PER_EU)))
+#define SNE_BATCH_OCCUPANCY \
+    __attribute__((amdgpu_waves_per_eu(LEN ? 1 : SNE_BATCH_WAVES_PER_EU)))
 #else
 #define SNE_BATCH_OCCUPANCY
 #endif
@@ -405,7 +416,14 @@ __device__ __forceinline__ void candidates(const float (&Nj)[8], const float (&r
 // are kept.  With nothing kept, the four +inf and four -inf pads give
 // -inf + inf = NaN, which the caller's norm test turns into the degenerate
 // normal.
-template <int KIND>
+// A neighbour gives no candidate when its raw value equals the centre's
+// (dZ = 0) or, under the lenient rule, when it is invalid (read as 0).
+template <bool LEN> __device__ __forceinline__ bool left_out(float zj, float zc) {
+    if constexpr (LEN) return zj == zc || zj == 0.f;
+    return zj == zc;
+}
+
+template <int KIND, bool LEN>
 __device__ __forceinline__ float median8(const float (&Nj)[8], const float (&rj)[8],
                                          const float (&zj)[8], float zc, bool general) {
     float t[8];
@@ -417,7 +435,7 @@ __device__ __forceinline__ float median8(const float (&Nj)[8], const float (&rj)
     float pad = kInf;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-        const bool drop = zj[j] == zc;
+        const bool drop = left_out<LEN>(zj[j], zc);
         t[j] = drop ? pad : t[j];
         pad = drop ? -pad : pad;
     }
@@ -428,7 +446,7 @@ __device__ __forceinline__ float median8(const float (&Nj)[8], const float (&rj)
 // 1/8 is exact, so a pixel with nothing left out gets the same bits whichever
 // path its wavefront takes.  With nothing kept the sum is +0 and 0 * (1/0)
 // is NaN, which the caller's norm test turns into the degenerate normal.
-template <int KIND>
+template <int KIND, bool LEN>
 __device__ __forceinline__ float mean8(const float (&Nj)[8], const float (&rj)[8],
                                        const float (&zj)[8], float zc, bool general) {
     float t[8];
@@ -440,7 +458,7 @@ __device__ __forceinline__ float mean8(const float (&Nj)[8], const float (&rj)[8
     int m = 0;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-        const bool drop = zj[j] == zc;
+        const bool drop = left_out<LEN>(zj[j], zc);
         t[j] = drop ? 0.f : t[j];
         m += drop ? 0 : 1;
     }
@@ -478,13 +496,52 @@ template <typename V> __device__ __forceinline__ void store_stream(void *p, cons
     }
 }
 
+// One gradient line under the lenient rule: samples zm (minus side), z0
+// (middle), zp (plus side) with the filtered values sm, s0, sp and the line's
+// central difference `both` (sp - sm, formed as the strict path forms it).
+// Returns the line's difference (0 if it has none) and sets `have`.
+template <int KIND>
+__device__ __forceinline__ float lenient_line(float zm, float z0, float zp, float sm, float s0,
+                                              float sp, float both, bool &have) {
+    const bool okm = zm > 0.f, ok0 = z0 > 0.f, okp = zp > 0.f;
+    float plus, minus;  // one-sided: 2 (sp - s0) and 2 (s0 - sm)
+    if constexpr (KIND == KIND_DISP) {
+        plus = 2.f * (zp - z0);
+        minus = 2.f * (z0 - zm);
+    } else {
+        plus = 2.f * ((z0 - zp) * (s0 * sp));
+        minus = 2.f * ((zm - z0) * (sm * s0));
+    }
+    have = (okm && okp) || (ok0 && (okm || okp));
+    return (okm && okp) ? both : (ok0 && okp) ? plus : (ok0 && okm) ? minus : 0.f;
+}
+
+// Lenient G from its lines (centre line c, side lines a and b, each 0 when
+// missing): the strict combination of the available lines, rescaled to the
+// full filter's weight.  With every line present it is the strict value.
+template <bool FD>
+__device__ __forceinline__ float lenient_combine(float c, bool hc, float a, bool ha, float b,
+                                                 bool hb, const GradW &w, bool &have) {
+    if constexpr (FD) {
+        have = hc;
+        return c;
+    } else {
+        const float g = fmaf(w.wa, a + b, c);
+        const int sides = (ha ? 1 : 0) + (hb ? 1 : 0);
+        have = hc || sides > 0;
+        const float scale = hc ? (sides == 2 ? 1.f : sides == 1 ? w.r[0] : w.r[1])
+                               : (sides == 2 ? w.r[2] : w.r[3]);
+        return g * scale;
+    }
+}
+
 // Output row r of a tile from the window (prev, cur, next); `pend` holds the
 // raw loads of row r + 1 on entry and those of row r + 1 + SNE_PREFETCH_ROWS
 // on exit.
-template <int KIND, bool FD, int AGG, int OUT, int PX, bool HALF>
+template <int KIND, bool FD, int AGG, int OUT, int PX, bool HALF, bool LEN>
 __device__ __forceinline__ void tile_row(const FrameDesc &f, const InBuf &ib, int r, int rend,
                                          int col, int col_off, int halo_off, const Edges &e,
-                                         float wa, float wb, RawRow<KIND, PX> &pend,
+                                         const GradW &gw, RawRow<KIND, PX> &pend,
                                          const RowState<PX> &prev, RowState<PX> &cur,
                                          RowState<PX> &next) {
     finish_row<KIND, PX, HALF>(pend, next.row, e);
@@ -514,7 +571,7 @@ __device__ __forceinline__ void tile_row(const FrameDesc &f, const InBuf &ib, in
     for (int k = 0; k < PX; ++k) {
         const int c = k + 1;
         const float zc = rc.z[c];
-        const bool valid = vmin3(rp.hmin[k], rc.hmin[k], rn.hmin[k]) > 0.f;
+        bool valid = vmin3(rp.hmin[k], rc.hmin[k], rn.hmin[k]) > 0.f;
         float Gu, Gv;
         if constexpr (FD) {
             Gu = rc.D[k];
@@ -522,8 +579,38 @@ __device__ __forceinline__ void tile_row(const FrameDesc &f, const InBuf &ib, in
         } else {
             // the 3-row filter divided by its centre weight (wa = side /
             // centre): n' scales as a whole, the normal does not change
-            Gu = fmaf(wa, rp.D[k] + rn.D[k], rc.D[k]);
-            Gv = fmaf(wa, V[c - 1] + V[c + 1], V[c]);
+            Gu = fmaf(gw.wa, rp.D[k] + rn.D[k], rc.D[k]);
+            Gv = fmaf(gw.wa, V[c - 1] + V[c + 1], V[c]);
+        }
+        bool lenient_wave = false;
+        if constexpr (LEN) {
+            // a valid pixel without a full window somewhere in the wavefront
+            if (__builtin_amdgcn_ballot_w64(!valid && zc > 0.f) != 0) {
+                lenient_wave = true;
+                bool hp = false, hc, hn = false, du, dv;
+                float Lp = 0.f, Ln = 0.f;
+                const float Lc = lenient_line<KIND>(rc.z[c - 1], zc, rc.z[c + 1], rc.s[c - 1],
+                                                    rc.s[c], rc.s[c + 1], rc.D[k], hc);
+                if constexpr (!FD) {
+                    Lp = lenient_line<KIND>(rp.z[c - 1], rp.z[c], rp.z[c + 1], rp.s[c - 1],
+                                            rp.s[c], rp.s[c + 1], rp.D[k], hp);
+                    Ln = lenient_line<KIND>(rn.z[c - 1], rn.z[c], rn.z[c + 1], rn.s[c - 1],
+                                            rn.s[c], rn.s[c + 1], rn.D[k], hn);
+                }
+                Gu = lenient_combine<FD>(Lc, hc, Lp, hp, Ln, hn, gw, du);
+                bool vl = false, vr = false, vc;
+                float Vl = 0.f, Vr = 0.f;
+                const float Vc = lenient_line<KIND>(rp.z[c], zc, rn.z[c], rp.s[c], rc.s[c],
+                                                    rn.s[c], V[c], vc);
+                if constexpr (!FD) {
+                    Vl = lenient_line<KIND>(rp.z[c - 1], rc.z[c - 1], rn.z[c - 1], rp.s[c - 1],
+                                            rc.s[c - 1], rn.s[c - 1], V[c - 1], vl);
+                    Vr = lenient_line<KIND>(rp.z[c + 1], rc.z[c + 1], rn.z[c + 1], rp.s[c + 1],
+                                            rc.s[c + 1], rn.s[c + 1], V[c + 1], vr);
+                }
+                Gv = lenient_combine<FD>(Vc, vc, Vl, vl, Vr, vr, gw, dv);
+                valid = zc > 0.f && du && dv;
+            }
         }
         const float fu = (float)(col + k) - f.u0;
         const float B = fmaf(fu, Gu, fv * Gv);
@@ -541,13 +628,15 @@ __device__ __forceinline__ void tile_row(const FrameDesc &f, const InBuf &ib, in
         // (signs do not matter here: the raw pair values are used)
         bool general = true;
         if constexpr (!kTieHeavy<KIND>) {
-            const float rmax = vmax8abs(rc.rE[c], rc.rE[c - 1], pd.rS[k], pu.rS[k], pd.rSE[c],
-                                        pu.rSE[k], pd.rSW[k], pu.rSW[c]);
-            const bool any_drop = !(rmax < kInf);
-            general = __builtin_amdgcn_ballot_w64(valid && any_drop) != 0;
+            if (!lenient_wave) {
+                const float rmax = vmax8abs(rc.rE[c], rc.rE[c - 1], pd.rS[k], pu.rS[k],
+                                            pd.rSE[c], pu.rSE[k], pd.rSW[k], pu.rSW[c]);
+                const bool any_drop = !(rmax < kInf);
+                general = __builtin_amdgcn_ballot_w64(valid && any_drop) != 0;
+            }
         }
-        const float phi = (AGG == AGG_MEAN) ? mean8<KIND>(Nj, rj, zj, zc, general)
-                                            : median8<KIND>(Nj, rj, zj, zc, general);
+        const float phi = (AGG == AGG_MEAN) ? mean8<KIND, LEN>(Nj, rj, zj, zc, general)
+                                            : median8<KIND, LEN>(Nj, rj, zj, zc, general);
         const float nx = f.fx * Gu, ny = f.fy * Gv, nz = B + phi;
         const float n2 = fmaf(nx, nx, fmaf(ny, ny, nz * nz));
         // nothing kept (phi NaN) or a zero vector: the degenerate normal
@@ -583,9 +672,9 @@ __device__ __forceinline__ void tile_row(const FrameDesc &f, const InBuf &ib, in
 // strip (the frame, hence the buffer resource, stays wave-uniform).  Rows
 // past the frame read as 0 and are not stored.  The row loop is unrolled three
 // times with the window's roles rotating, so no register state is copied.
-template <int KIND, bool FD, int AGG, int OUT, int PX, bool HALF>
-__device__ __forceinline__ void run_tile(const FrameDesc &f, int c0, int r0, int rows, float wa,
-                                         float wb) {
+template <int KIND, bool FD, int AGG, int OUT, int PX, bool HALF, bool LEN>
+__device__ __forceinline__ void run_tile(const FrameDesc &f, int c0, int r0, int rows,
+                                         const GradW &gw) {
     using T = typename Raw<KIND>::T;
     constexpr int kLanes = HALF ? kWave / 2 : kWave;
     const int lane = threadIdx.x & (kWave - 1);
@@ -611,9 +700,9 @@ __device__ __forceinline__ void run_tile(const FrameDesc &f, int c0, int r0, int
     finish_row<KIND, PX, HALF>(p0, B.row, e);
     make_pairs<PX>(A.row, B.row, A.below);
     load_raw<KIND, PX>(ib, rb + 1, col_off, halo_off, p0);
-#define SNE_ROW(I, P, X, Y, Z)                                                                   \
-    tile_row<KIND, FD, AGG, OUT, PX, HALF>(f, ib, rb + (I), rend, col, col_off, halo_off, e, wa, \
-                                           wb, P, X, Y, Z)
+#define SNE_ROW(I, P, X, Y, Z)                                                                 \
+    tile_row<KIND, FD, AGG, OUT, PX, HALF, LEN>(f, ib, rb + (I), rend, col, col_off, halo_off, e, \
+                                                gw, P, X, Y, Z)
 #if SNE_PREFETCH_ROWS == 1
     for (int i = 0; i < n; i += 3) {
         SNE_ROW(i, p0, A, B, C);
@@ -650,7 +739,7 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     return x * q + min(x, rem) + i;
 }
 
-template <int KIND, bool FD, int AGG, int OUT, int PX, bool HALF>
+template <int KIND, bool FD, int AGG, int OUT, int PX, bool HALF, bool LEN>
 __global__ __launch_bounds__(kBlock) SNE_OCCUPANCY void sne_uniform_kernel(UniformArgs a) {
     const int b = a.xcd_remap ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     // wave-uniform by construction; readfirstlane lets the compiler keep the
@@ -670,8 +759,8 @@ __global__ __launch_bounds__(kBlock) SNE_OCCUPANCY void sne_uniform_kernel(Unifo
     if (f.mask) f.mask = a.f.mask + frame * a.mask_fstride;
     // half-wave mode: a "band" is a pair of bands and a strip is 32 PX wide
     const int r0 = band * a.rows * (HALF ? 2 : 1);
-    run_tile<KIND, FD, AGG, OUT, PX, HALF>(f, strip * (HALF ? kWave / 2 : kWave) * PX, r0, a.rows,
-                                           a.wa, a.wb);
+    run_tile<KIND, FD, AGG, OUT, PX, HALF, LEN>(f, strip * (HALF ? kWave / 2 : kWave) * PX, r0,
+                                                a.rows, a.gw);
 }
 
 // A value loaded through a generic pointer counts as lane-varying for the
@@ -716,7 +805,7 @@ __device__ __forceinline__ int find_frame(const int32_t *tile_start, int nframes
 // until all are drained.  The queues hold contiguous tile ranges, so
 // neighbouring tiles (which share halo rows) mostly run on one XCD and meet
 // in its L2, and the atomic increments are spread over eight addresses.
-template <int KIND, bool FD, int AGG, int OUT, int PX, bool HALF>
+template <int KIND, bool FD, int AGG, int OUT, int PX, bool HALF, bool LEN>
 __global__ __launch_bounds__(kBlock) SNE_BATCH_OCCUPANCY void sne_batch_kernel(BatchArgs a) {
     const int lane = threadIdx.x & (kWave - 1);
     BatchHeader *head = static_cast<BatchHeader *>(a.table);
@@ -758,93 +847,84 @@ __global__ __launch_bounds__(kBlock) SNE_BATCH_OCCUPANCY void sne_batch_kernel(B
                 const int band = local / ns;
                 const int strip = local - band * ns;
                 const int r0 = band * a.rows * (HALF ? 2 : 1);
-                run_tile<KIND, FD, AGG, OUT, PX, HALF>(f, strip * (HALF ? kWave / 2 : kWave) * PX,
-                                                       r0, a.rows, a.wa, a.wb);
+                run_tile<KIND, FD, AGG, OUT, PX, HALF, LEN>(
+                    f, strip * (HALF ? kWave / 2 : kWave) * PX, r0, a.rows, a.gw);
             }
         }
     }
 }
 
-template <int KIND, bool FD, int AGG, int OUT>
+template <int KIND, bool FD, int AGG, int OUT, bool LEN>
 hipError_t uniform_px(int px, const UniformArgs &a, int grid, hipStream_t s) {
     // px: columns per lane, + 100 for the half-wave mode
     switch (px) {
-    case 1: hipLaunchKernelGGL((sne_uniform_kernel<KIND, FD, AGG, OUT, 1, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((sne_uniform_kernel<KIND, FD, AGG, OUT, 2, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((sne_uniform_kernel<KIND, FD, AGG, OUT, 4, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 101: hipLaunchKernelGGL((sne_uniform_kernel<KIND, FD, AGG, OUT, 1, true>), dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 102: hipLaunchKernelGGL((sne_uniform_kernel<KIND, FD, AGG, OUT, 2, true>), dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 104: hipLaunchKernelGGL((sne_uniform_kernel<KIND, FD, AGG, OUT, 4, true>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((sne_uniform_kernel<KIND, FD, AGG, OUT, 1, false, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((sne_uniform_kernel<KIND, FD, AGG, OUT, 2, false, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((sne_uniform_kernel<KIND, FD, AGG, OUT, 4, false, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 101: hipLaunchKernelGGL((sne_uniform_kernel<KIND, FD, AGG, OUT, 1, true, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 102: hipLaunchKernelGGL((sne_uniform_kernel<KIND, FD, AGG, OUT, 2, true, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 104: hipLaunchKernelGGL((sne_uniform_kernel<KIND, FD, AGG, OUT, 4, true, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <int KIND, bool FD, int AGG, int OUT>
+template <int KIND, bool FD, int AGG, int OUT, bool LEN>
 hipError_t batch_px(int px, const BatchArgs &a, int grid, hipStream_t s) {
     // px: columns per lane, + 100 for the half-wave mode
     switch (px) {
-    case 1: hipLaunchKernelGGL((sne_batch_kernel<KIND, FD, AGG, OUT, 1, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((sne_batch_kernel<KIND, FD, AGG, OUT, 2, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((sne_batch_kernel<KIND, FD, AGG, OUT, 4, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 101: hipLaunchKernelGGL((sne_batch_kernel<KIND, FD, AGG, OUT, 1, true>), dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 102: hipLaunchKernelGGL((sne_batch_kernel<KIND, FD, AGG, OUT, 2, true>), dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 104: hipLaunchKernelGGL((sne_batch_kernel<KIND, FD, AGG, OUT, 4, true>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((sne_batch_kernel<KIND, FD, AGG, OUT, 1, false, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((sne_batch_kernel<KIND, FD, AGG, OUT, 2, false, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((sne_batch_kernel<KIND, FD, AGG, OUT, 4, false, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 101: hipLaunchKernelGGL((sne_batch_kernel<KIND, FD, AGG, OUT, 1, true, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 102: hipLaunchKernelGGL((sne_batch_kernel<KIND, FD, AGG, OUT, 2, true, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 104: hipLaunchKernelGGL((sne_batch_kernel<KIND, FD, AGG, OUT, 4, true, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <int KIND, bool FD, int AGG, int OUT>
+template <int KIND, bool FD, int AGG, int OUT, bool LEN>
 hipError_t occupancy_px(int px, int *blocks) {
     const void *f = nullptr;
     switch (px) {
-    case 1: f = reinterpret_cast<const void *>(&sne_batch_kernel<KIND, FD, AGG, OUT, 1, false>); break;
-    case 2: f = reinterpret_cast<const void *>(&sne_batch_kernel<KIND, FD, AGG, OUT, 2, false>); break;
-    case 4: f = reinterpret_cast<const void *>(&sne_batch_kernel<KIND, FD, AGG, OUT, 4, false>); break;
-    case 101: f = reinterpret_cast<const void *>(&sne_batch_kernel<KIND, FD, AGG, OUT, 1, true>); break;
-    case 102: f = reinterpret_cast<const void *>(&sne_batch_kernel<KIND, FD, AGG, OUT, 2, true>); break;
-    case 104: f = reinterpret_cast<const void *>(&sne_batch_kernel<KIND, FD, AGG, OUT, 4, true>); break;
+    case 1: f = reinterpret_cast<const void *>(&sne_batch_kernel<KIND, FD, AGG, OUT, 1, false, LEN>); break;
+    case 2: f = reinterpret_cast<const void *>(&sne_batch_kernel<KIND, FD, AGG, OUT, 2, false, LEN>); break;
+    case 4: f = reinterpret_cast<const void *>(&sne_batch_kernel<KIND, FD, AGG, OUT, 4, false, LEN>); break;
+    case 101: f = reinterpret_cast<const void *>(&sne_batch_kernel<KIND, FD, AGG, OUT, 1, true, LEN>); break;
+    case 102: f = reinterpret_cast<const void *>(&sne_batch_kernel<KIND, FD, AGG, OUT, 2, true, LEN>); break;
+    case 104: f = reinterpret_cast<const void *>(&sne_batch_kernel<KIND, FD, AGG, OUT, 4, true, LEN>); break;
     default: return hipErrorInvalidValue;
     }
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, f, kBlock, 0);
 }
 
-#define SNE_DISPATCH(FN, ARGS)                                                              \
-    template <int KIND>                                                                     \
-    hipError_t FN##_variant(const Variant &v, const ARGS &a, int grid, hipStream_t s) {     \
-        const bool fd = v.grad == 0;                                                        \
-        if (fd) {                                                                           \
-            if (v.agg == AGG_MEAN)                                                          \
-                return v.out == OUT_F32 ? FN##_px<KIND, true, AGG_MEAN, OUT_F32>(v.px, a, grid, s) \
-                                        : FN##_px<KIND, true, AGG_MEAN, OUT_F16>(v.px, a, grid, s); \
-            return v.out == OUT_F32 ? FN##_px<KIND, true, AGG_MEDIAN, OUT_F32>(v.px, a, grid, s)   \
-                                    : FN##_px<KIND, true, AGG_MEDIAN, OUT_F16>(v.px, a, grid, s);  \
-        }                                                                                   \
-        if (v.agg == AGG_MEAN)                                                              \
-            return v.out == OUT_F32 ? FN##_px<KIND, false, AGG_MEAN, OUT_F32>(v.px, a, grid, s)    \
-                                    : FN##_px<KIND, false, AGG_MEAN, OUT_F16>(v.px, a, grid, s);   \
-        return v.out == OUT_F32 ? FN##_px<KIND, false, AGG_MEDIAN, OUT_F32>(v.px, a, grid, s)      \
-                                : FN##_px<KIND, false, AGG_MEDIAN, OUT_F16>(v.px, a, grid, s);     \
-    }
+// Dispatch on the runtime variant: filter class, aggregation, output type
+// and rule, then the tile's column class.  FN is uniform_px, batch_px or
+// occupancy_px; ARGS... are their arguments after px.
+#define SNE_DISPATCH_LEN(FN, KIND, FD, AGG, OUT, v, ...)                                   \
+    (((v).kind & kLenientFlag) ? FN<KIND, FD, AGG, OUT, true>((v).px, __VA_ARGS__)         \
+                              : FN<KIND, FD, AGG, OUT, false>((v).px, __VA_ARGS__))
+#define SNE_DISPATCH_OUT(FN, KIND, FD, AGG, v, ...)                                        \
+    ((v).out == OUT_F32 ? SNE_DISPATCH_LEN(FN, KIND, FD, AGG, OUT_F32, v, __VA_ARGS__)     \
+                        : SNE_DISPATCH_LEN(FN, KIND, FD, AGG, OUT_F16, v, __VA_ARGS__))
+#define SNE_DISPATCH_AGG(FN, KIND, FD, v, ...)                                             \
+    ((v).agg == AGG_MEAN ? SNE_DISPATCH_OUT(FN, KIND, FD, AGG_MEAN, v, __VA_ARGS__)        \
+                         : SNE_DISPATCH_OUT(FN, KIND, FD, AGG_MEDIAN, v, __VA_ARGS__))
+#define SNE_DISPATCH(FN, KIND, v, ...)                                                     \
+    ((v).grad == 0 ? SNE_DISPATCH_AGG(FN, KIND, true, v, __VA_ARGS__)                      \
+                   : SNE_DISPATCH_AGG(FN, KIND, false, v, __VA_ARGS__))
 
-SNE_DISPATCH(uniform, UniformArgs)
-SNE_DISPATCH(batch, BatchArgs)
-
+template <int KIND>
+hipError_t uniform_variant(const Variant &v, const UniformArgs &a, int grid, hipStream_t s) {
+    return SNE_DISPATCH(uniform_px, KIND, v, a, grid, s);
+}
+template <int KIND>
+hipError_t batch_variant(const Variant &v, const BatchArgs &a, int grid, hipStream_t s) {
+    return SNE_DISPATCH(batch_px, KIND, v, a, grid, s);
+}
 template <int KIND> hipError_t occupancy_variant(const Variant &v, int *blocks) {
-    const bool fd = v.grad == 0;
-    if (fd) {
-        if (v.agg == AGG_MEAN)
-            return v.out == OUT_F32 ? occupancy_px<KIND, true, AGG_MEAN, OUT_F32>(v.px, blocks)
-                                    : occupancy_px<KIND, true, AGG_MEAN, OUT_F16>(v.px, blocks);
-        return v.out == OUT_F32 ? occupancy_px<KIND, true, AGG_MEDIAN, OUT_F32>(v.px, blocks)
-                                : occupancy_px<KIND, true, AGG_MEDIAN, OUT_F16>(v.px, blocks);
-    }
-    if (v.agg == AGG_MEAN)
-        return v.out == OUT_F32 ? occupancy_px<KIND, false, AGG_MEAN, OUT_F32>(v.px, blocks)
-                                : occupancy_px<KIND, false, AGG_MEAN, OUT_F16>(v.px, blocks);
-    return v.out == OUT_F32 ? occupancy_px<KIND, false, AGG_MEDIAN, OUT_F32>(v.px, blocks)
-                            : occupancy_px<KIND, false, AGG_MEDIAN, OUT_F16>(v.px, blocks);
+    return SNE_DISPATCH(occupancy_px, KIND, v, blocks);
 }
 
 }  // namespace

@@ -111,7 +111,7 @@ public:
         a.ktable = reinterpret_cast<const float4 *>(ctx->d_K);
         a.rows = tile.rows;
         a.chunk = 1;
-        grad_weights(cfg.grad, a.wa, a.wb);
+        grad_weights(cfg.grad, a.gw);
         return a;
     }
 

@@ -231,6 +231,27 @@ def _enum(table, key, what):
     return table[key]
 
 
+SNE_LENIENT = 0x100  # include/sne.h
+
+
+def _kind(kind) -> int:
+    """Kind code; a "+lenient" suffix (e.g. "depth_u16+lenient") ORs in
+    SNE_LENIENT, the rule for holes and the frame border."""
+    if isinstance(kind, int):
+        return kind
+    base, plus, rule = kind.partition("+")
+    code = _enum(KIND, base, "kind")
+    if plus:
+        if rule != "lenient":
+            raise ValueError("unknown kind suffix %r" % rule)
+        code |= SNE_LENIENT
+    return code
+
+
+def _dtype(kind_i: int):
+    return KIND_DTYPE[kind_i & ~SNE_LENIENT]
+
+
 def _row_pitch(t: torch.Tensor) -> int:
     """Row pitch (elements) of a [..., H, W] tensor with unit column stride."""
     if t.stride(-1) != 1:
@@ -275,14 +296,14 @@ class Context:
     def get_tile(self, H, W, B=1, kind="depth_f32", grad="fd", agg="mean",
                  out="f32") -> Tuple[int, int, int]:
         t = Tile()
-        check("sne_get_tile", lib().sne_get_tile(self._h, H, W, B, _enum(KIND, kind, "kind"),
+        check("sne_get_tile", lib().sne_get_tile(self._h, H, W, B, _kind(kind),
                                                  _enum(GRAD, grad, "grad"), _enum(AGG, agg, "agg"),
                                                  _enum(OUT, out, "out"), ctypes.byref(t)))
         return t.cols_per_lane, t.rows, t.lanes
 
     def autotune(self, H, W, B=1, kind="depth_f32", grad="fd", agg="mean", out="f32"):
         t = Tile()
-        check("sne_autotune", lib().sne_autotune(self._h, H, W, B, _enum(KIND, kind, "kind"),
+        check("sne_autotune", lib().sne_autotune(self._h, H, W, B, _kind(kind),
                                                  _enum(GRAD, grad, "grad"), _enum(AGG, agg, "agg"),
                                                  _enum(OUT, out, "out"), ctypes.byref(t)))
         return t.cols_per_lane, t.rows, t.lanes
@@ -292,7 +313,7 @@ class Context:
         are written); returns (cols_per_lane, rows, lanes)."""
         t = Tile()
         check("sne_autotune_batched",
-              lib().sne_autotune_batched(self._h, descs, len(descs), _enum(KIND, kind, "kind"),
+              lib().sne_autotune_batched(self._h, descs, len(descs), _kind(kind),
                                          _enum(GRAD, grad, "grad"), _enum(AGG, agg, "agg"),
                                          _enum(OUT, out, "out"), ctypes.byref(t)))
         return t.cols_per_lane, t.rows, t.lanes
@@ -353,7 +374,7 @@ class Context:
                         masks: Optional[Sequence[Optional[torch.Tensor]]] = None):
         """Descriptor array (host, ctypes) of an uneven batch, reusable across
         launches, with the outputs it points to."""
-        kind_i = _enum(KIND, kind, "kind")
+        kind_i = _kind(kind)
         out_i = _enum(OUT, out, "out")
         n = len(frames)
         if normals is None:
@@ -365,8 +386,8 @@ class Context:
         descs = (FrameDesc * n)()
         for i, f in enumerate(frames):
             _on_gpu(f, normals[i], masks[i])
-            if f.dtype != KIND_DTYPE[kind_i]:
-                raise TypeError("frame %d: kind %s needs %s" % (i, kind, KIND_DTYPE[kind_i]))
+            if f.dtype != _dtype(kind_i):
+                raise TypeError("frame %d: kind %s needs %s" % (i, kind, _dtype(kind_i)))
             H, W = f.shape[-2:]
             m = masks[i]
             descs[i] = FrameDesc(f.data_ptr(), normals[i].data_ptr(),
@@ -379,7 +400,7 @@ class Context:
                     stream=None):
         """sne_estimate_batched on a prepared descriptor array."""
         check("sne_estimate_batched",
-              lib().sne_estimate_batched(self._h, descs, len(descs), _enum(KIND, kind, "kind"),
+              lib().sne_estimate_batched(self._h, descs, len(descs), _kind(kind),
                                          _enum(GRAD, grad, "grad"), _enum(AGG, agg, "agg"),
                                          _enum(OUT, out, "out"), _stream(stream)))
 
@@ -401,7 +422,7 @@ class Server:
                  max_inflight=3, max_batch_frames=256, max_batch_pixels=64 << 20,
                  hbm_budget_bytes=4 << 30, queue_capacity=65536, use_graphs=True):
         self.ctx = ctx
-        self.kind, self.out = _enum(KIND, kind, "kind"), _enum(OUT, out, "out")
+        self.kind, self.out = _kind(kind), _enum(OUT, out, "out")
         cfg = ServerConfig(self.kind, _enum(GRAD, grad, "grad"), _enum(AGG, agg, "agg"),
                            self.out, max_inflight, max_batch_frames, max_batch_pixels,
                            hbm_budget_bytes, queue_capacity, 1 if use_graphs else 0, 0)
@@ -416,8 +437,8 @@ class Server:
         current stream), so the batch reads the frame only after the work
         enqueued there so far; frame and event are kept until release."""
         _on_gpu(frame)
-        if frame.dtype != KIND_DTYPE[self.kind]:
-            raise TypeError("server kind needs %s frames" % KIND_DTYPE[self.kind])
+        if frame.dtype != _dtype(self.kind):
+            raise TypeError("server kind needs %s frames" % _dtype(self.kind))
         H, W = frame.shape
         ev = torch.cuda.Event()
         ev.record(producer if producer is not None else torch.cuda.current_stream(frame.device))
@@ -481,7 +502,7 @@ class Server:
             Ps[s_] = _row_pitch(fs[0])
             for k, f in enumerate(fs):
                 _on_gpu(f)
-                if tuple(f.shape) != (Hs[s_], Ws[s_]) or f.dtype != KIND_DTYPE[self.kind]:
+                if tuple(f.shape) != (Hs[s_], Ws[s_]) or f.dtype != _dtype(self.kind):
                     raise ValueError("stream %d: frames differ in shape or dtype" % s_)
                 ptrs[s_ * ring + k] = f.data_ptr()
         cfg = LoadgenConfig(ns, n_producers, float(total_rate), float(duration_s), int(seed),
@@ -567,11 +588,11 @@ def _outputs(raw, out_i, normals, mask, want_mask):
 def estimate(raw: torch.Tensor, K, kind="depth_f32", grad="fd", agg="mean", out="f32",
              normals=None, mask=None, want_mask=True, stream=None, ctx: Optional[Context] = None):
     """sne_estimate on a [H, W] device tensor; returns (normals [3,H,W], mask)."""
-    kind_i, out_i = _enum(KIND, kind, "kind"), _enum(OUT, out, "out")
+    kind_i, out_i = _kind(kind), _enum(OUT, out, "out")
     if raw.dim() != 2:
         raise ValueError("expected [H, W]")
-    if raw.dtype != KIND_DTYPE[kind_i]:
-        raise TypeError("kind %s needs %s input" % (kind, KIND_DTYPE[kind_i]))
+    if raw.dtype != _dtype(kind_i):
+        raise TypeError("kind %s needs %s input" % (kind, _dtype(kind_i)))
     normals, mask = _outputs(raw, out_i, normals, mask, want_mask)
     H, W = raw.shape
     Kc = _K(K)
@@ -589,11 +610,11 @@ def estimate_uniform(raw: torch.Tensor, K, kind="depth_f32", grad="fd", agg="mea
                      ctx: Optional[Context] = None):
     """sne_estimate_uniform on a [B, H, W] device tensor; returns
     (normals [B,3,H,W], mask [B,H,W])."""
-    kind_i, out_i = _enum(KIND, kind, "kind"), _enum(OUT, out, "out")
+    kind_i, out_i = _kind(kind), _enum(OUT, out, "out")
     if raw.dim() != 3:
         raise ValueError("expected [B, H, W]")
-    if raw.dtype != KIND_DTYPE[kind_i]:
-        raise TypeError("kind %s needs %s input" % (kind, KIND_DTYPE[kind_i]))
+    if raw.dtype != _dtype(kind_i):
+        raise TypeError("kind %s needs %s input" % (kind, _dtype(kind_i)))
     normals, mask = _outputs(raw, out_i, normals, mask, want_mask)
     B, H, W = raw.shape
     Kc = _K(K)

@@ -22,6 +22,8 @@ def test_header_constants_match_binding():
     text = open(sne.HEADER).read()
     m = re.search(r"#define SNE_NOALLOC_MAX_FRAMES (\d+)", text)
     assert m and int(m.group(1)) == sne.SNE_NOALLOC_MAX_FRAMES
+    m = re.search(r"#define SNE_LENIENT (0x[0-9a-f]+)", text)
+    assert m and int(m.group(1), 16) == sne.SNE_LENIENT
     for name in ("SNE_ERR_ARG", "SNE_ERR_BUDGET", "SNE_ERR_STATE"):
         m = re.search(r"#define %s \((-\d+)\)" % name, text)
         assert m and int(m.group(1)) == getattr(sne, name), name
@@ -52,6 +54,7 @@ FAKE = 0x10000  # never dereferenced: every call below fails validation first
     dict(out_pitch=5), dict(mask_pitch=5), dict(kind=7), dict(grad=-1), dict(agg=2),
     dict(out=2), dict(K=_K(fx=0.0)), dict(K=_K(fy=-1.0)), dict(K=_K(u0=float("nan"))),
     dict(K=_K(fx=float("inf"))), dict(kind=3, K=_K(fx=500.0, fy=501.0)), dict(Knull=True),
+    dict(kind=0x200), dict(kind=0x104), dict(kind=0x103, K=_K(fx=500.0, fy=501.0)),
 ])
 def test_estimate_argument_errors(case):
     L = sne.lib()
@@ -208,3 +211,10 @@ def test_binding_rejects_host_tensors():
 ])
 def test_bandwidth_probe_argument_errors(mode, n, src, dst, mask):
     assert sne.lib().sne_bandwidth_probe(mode, src, dst, mask, n, None) == sne.SNE_ERR_ARG
+
+
+def test_lenient_kind_suffix():
+    assert sne._kind("depth_u16+lenient") == 1 | sne.SNE_LENIENT
+    assert sne._kind("disparity_f32") == 3
+    with pytest.raises(ValueError):
+        sne._kind("depth_u16+loose")
