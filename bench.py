@@ -426,6 +426,7 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-disparity", action="store_true")
     ap.add_argument("--no-lenient", action="store_true")
+    ap.add_argument("--no-packed", action="store_true")
     ap.add_argument("--disparity-steps", type=int, default=300)
     ap.add_argument("--serving-rate", type=float, default=0.0,
                     help="run the serving loop at this one offered rate (FD-mean) only")
@@ -526,6 +527,30 @@ def main():
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
                          "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
                          "algorithmic_bytes_per_launch": bytes_per_launch}}
+    if not args.no_packed:
+        log("packed colour + normals on the same batches")
+        rgbs = [torch.randint(0, 256, (B, H, W, 4), dtype=torch.uint8, device="cuda")
+                for _ in range(NBUF)]
+        pks = [torch.empty((B, H, W, 8), dtype=torch.float16, device="cuda") for _ in range(NBUF)]
+
+        def step_pk(i):
+            sne.estimate_rgbn(bufs[i % NBUF][0], K, "depth_f32", args.grad, args.agg,
+                              rgb=rgbs[i % NBUF], out=pks[i % NBUF], ctx=ctx)
+
+        psteps = max(args.steps // 3, 10)
+        wall_p, ev_p = time_launches(torch, step_pk, max(args.warmup // 3, 5), psteps)
+        pbytes = px * (4 + 4 + 16)
+        gbs = pbytes / (ev_p / psteps) / 1e9
+        res["packed_batch"] = {
+            "workload": workload + "_rgbn_packed",
+            "note": "4 B depth + 4 B RGBX in, 16 B out per pixel (R, G, B, mask, n_x, n_y, n_z, "
+                    "0 as FP16): the network-input layout, in one launch",
+            "us_per_launch": round(ev_p / psteps * 1e6, 2),
+            "mpix_per_s": round(px * psteps / ev_p / 1e6, 1),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                         "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                         "algorithmic_bytes_per_launch": pbytes}}
+        del rgbs, pks
     log("copy calibration")
     res["copy_calibration"] = copy_calibration(torch)
     log("streaming-pattern calibration (hand-written probes)")

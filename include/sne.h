@@ -137,6 +137,23 @@ int sne_estimate_uniform(sne_ctx *ctx, const void *in, int32_t B, int32_t H, int
                          int64_t out_pitch, int64_t out_frame_stride, uint8_t *mask,
                          int64_t mask_pitch, int64_t mask_frame_stride, void *stream);
 
+/* Normals packed for a network that takes colour and geometry together (the
+ * paper's applications feed estimated normals to CNNs, Sec. V): B frames as
+ * for sne_estimate_uniform, written as [B][H][out_pitch] pixels of 8 FP16
+ * channels, 16 bytes each:
+ *     R, G, B (colour bytes / 255), mask (1 or 0), n_x, n_y, n_z, 0
+ * with the normal channels bitwise equal to sne_estimate_uniform's FP16
+ * output.  rgb: [B][H][rgb_pitch bytes] of RGBX bytes (4 per pixel, the
+ * fourth ignored), or NULL for zero colour channels.  out must be 16-byte
+ * aligned; out_pitch and out_frame_stride count pixels; the separate u8 mask
+ * may be NULL.  kind may carry SNE_LENIENT.  One launch. */
+int sne_estimate_rgbn(sne_ctx *ctx, const void *in, int32_t B, int32_t H, int32_t W,
+                      int64_t in_pitch, int64_t in_frame_stride, const sne_intrinsics *K,
+                      int kind, int grad, int agg, const void *rgb, int64_t rgb_pitch,
+                      int64_t rgb_frame_stride, void *out, int64_t out_pitch,
+                      int64_t out_frame_stride, uint8_t *mask, int64_t mask_pitch,
+                      int64_t mask_frame_stride, void *stream);
+
 /* Descriptor of one frame of an uneven batch (all device pointers). */
 typedef struct {
     const void *in;          /* [H][in_pitch]                              */

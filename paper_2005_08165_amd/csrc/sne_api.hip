@@ -200,6 +200,8 @@ FrameDesc make_desc(const void *in, void *out, uint8_t *mask, int H, int W, int6
     f.v0 = K.v0;
     f.k_index = 0;
     f.pad_ = 0;
+    f.rgb = nullptr;
+    f.rgb_pitch = 0;
     return f;
 }
 
@@ -228,31 +230,58 @@ int scan_batch(const sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind,
 
 namespace {
 
+// Packed colour + normal output: RGBX bytes in (optional), 16 bytes per
+// pixel out.  Checked by sne_estimate_rgbn before uniform_impl runs.
+struct RgbArgs {
+    const void *rgb = nullptr;
+    int64_t pitch = 0, fstride = 0;  // bytes
+};
+
 int uniform_impl(sne_ctx *ctx, const void *in, int32_t B, int32_t H, int32_t W, int64_t in_pitch,
                  int64_t in_fs, const sne_intrinsics *K, int kind, int grad, int agg, int out_type,
                  void *normals, int64_t out_pitch, int64_t out_fs, uint8_t *mask,
-                 int64_t mask_pitch, int64_t mask_fs, void *stream, const TileChoice *force) {
-    if (!valid_enum(kind, grad, agg, out_type) || !valid_K(K, kind)) return SNE_ERR_ARG;
+                 int64_t mask_pitch, int64_t mask_fs, void *stream, const TileChoice *force,
+                 const RgbArgs *rgb = nullptr) {
+    const bool packed = rgb != nullptr;
+    if (!(packed ? valid_enum(kind, grad, agg, SNE_OUT_F32) : valid_enum(kind, grad, agg, out_type))
+        || !valid_K(K, kind))
+        return SNE_ERR_ARG;
     if (B < 0 || H < 1 || W < 1 || in_pitch < W || out_pitch < W) return SNE_ERR_ARG;
     if (mask && mask_pitch < W) return SNE_ERR_ARG;
     if (B == 0) return SNE_OK;  // an empty batch: the pointers may be NULL
     if (!in || !normals) return SNE_ERR_ARG;
     const int64_t plane = (int64_t)H * out_pitch;
-    if (B > 1 && (in_fs < (int64_t)H * in_pitch || out_fs < 3 * plane ||
-                  (mask && mask_fs < (int64_t)H * mask_pitch)))
+    // a packed frame is [H][out_pitch] pixels of 8 FP16 channels
+    const int64_t out_frame = packed ? 8 * plane : 3 * plane;
+    if (B > 1 && (in_fs < (int64_t)H * in_pitch || out_fs < out_frame ||
+                  (mask && mask_fs < (int64_t)H * mask_pitch) ||
+                  (packed && rgb->rgb && rgb->fstride < (int64_t)H * rgb->pitch)))
         return SNE_ERR_ARG;
+    int64_t rgb_fs = packed ? rgb->fstride : 0;
     if (B == 1) {
         in_fs = 0;
         out_fs = 0;
         mask_fs = 0;
+        rgb_fs = 0;
     }
     // the kernels address one frame's input with 32-bit byte offsets
-    if (!frame_fits(H, in_pitch, kind, out_pitch, out_type, mask ? mask_pitch : 0))
+    if (!frame_fits(H, in_pitch, kind, packed ? 8 * out_pitch : out_pitch,
+                    packed ? SNE_OUT_F16 : out_type, mask ? mask_pitch : 0) ||
+        (packed && (H + 2) * rgb->pitch >= INT32_MAX))
         return SNE_ERR_UNSUPPORTED;
-    Variant v{kind, grad, agg, out_type, 1};
-    const int pxmax = max_px(in, normals, mask, W, in_pitch, out_pitch, mask_pitch, in_fs, out_fs,
-                             mask_fs, plane, kind, out_type);
+    Variant v{kind, grad, agg, packed ? (int)OUT_RGBN : out_type, 1};
+    int pxmax = max_px(in, normals, mask, W, in_pitch, packed ? 8 * out_pitch : out_pitch,
+                       mask_pitch, in_fs, out_fs, mask_fs, packed ? 8 * plane : plane, kind,
+                       packed ? SNE_OUT_F16 : out_type);
+    if (packed && rgb->rgb)  // RGBX vector loads of px pixels
+        while (pxmax > 1 && (rgb->pitch % (4 * pxmax) || rgb_fs % (4 * pxmax) ||
+                             !aligned(rgb->rgb, 4 * pxmax)))
+            pxmax >>= 1;
     TileChoice t = force ? *force : pick_tile(ctx, H, W, B, v, pxmax);
+    // The packed pixels are 16 bytes each: with one column per lane a store
+    // instruction covers 1 KiB of contiguous output, with more columns per
+    // lane it scatters 16-byte pieces (measured 3.6x slower at 4 columns).
+    if (packed && !force && !(ctx && ctx->forced.rows > 0)) t = TileChoice{1, 8, 1, 0};
     if (t.px > pxmax || t.rows < 1) return SNE_ERR_ARG;
     v.px = kernel_px(t);
     UniformArgs a;
@@ -260,6 +289,11 @@ int uniform_impl(sne_ctx *ctx, const void *in, int32_t B, int32_t H, int32_t W, 
     a.in_fstride = in_fs;
     a.out_fstride = out_fs;
     a.mask_fstride = mask_fs;
+    a.rgb_fstride = rgb_fs;
+    if (packed) {
+        a.f.rgb = rgb->rgb;
+        a.f.rgb_pitch = rgb->pitch;
+    }
     a.B = B;
     a.nstrips = tile_nstrips(W, t);
     a.nbands = tile_nbands(H, t);
@@ -590,6 +624,25 @@ int sne_estimate_uniform(sne_ctx *ctx, const void *in, int32_t B, int32_t H, int
     return uniform_impl(ctx, in, B, H, W, in_pitch, in_frame_stride, K, kind, grad, agg, out_type,
                         normals, out_pitch, out_frame_stride, mask, mask_pitch, mask_frame_stride,
                         stream, nullptr);
+}
+
+int sne_estimate_rgbn(sne_ctx *ctx, const void *in, int32_t B, int32_t H, int32_t W,
+                      int64_t in_pitch, int64_t in_frame_stride, const sne_intrinsics *K,
+                      int kind, int grad, int agg, const void *rgb, int64_t rgb_pitch,
+                      int64_t rgb_frame_stride, void *out, int64_t out_pitch,
+                      int64_t out_frame_stride, uint8_t *mask, int64_t mask_pitch,
+                      int64_t mask_frame_stride, void *stream) {
+    if (out && !aligned(out, 16)) return SNE_ERR_ARG;
+    if (rgb && (rgb_pitch < 4 * (int64_t)W || rgb_pitch % 4 || !aligned(rgb, 4)))
+        return SNE_ERR_ARG;
+    RgbArgs r;
+    r.rgb = rgb;
+    r.pitch = rgb ? rgb_pitch : 0;
+    r.fstride = rgb ? rgb_frame_stride : 0;
+    // the packed frame's stride counts pixels of 8 channels, in FP16 elements
+    return uniform_impl(ctx, in, B, H, W, in_pitch, in_frame_stride, K, kind, grad, agg,
+                        SNE_OUT_F16, out, out_pitch, 8 * out_frame_stride, mask, mask_pitch,
+                        mask_frame_stride, stream, nullptr, &r);
 }
 
 int sne_set_intrinsics_table(sne_ctx *ctx, const sne_intrinsics *K, int32_t n) {

@@ -22,6 +22,9 @@ struct FrameDesc {
     float fx, fy, u0, v0;
     int32_t k_index;  // uneven batches: row of the intrinsics table
     int32_t pad_;
+    // packed RGB + normal output only: RGBX bytes beside the input (or null)
+    const void *rgb;
+    int64_t rgb_pitch;  // bytes
 };
 
 // Gradient-filter weights as the kernels use them: a 3-row filter divided by
@@ -38,6 +41,7 @@ struct GradW {
 struct UniformArgs {
     FrameDesc f;
     int64_t in_fstride, out_fstride, mask_fstride;
+    int64_t rgb_fstride;            // bytes
     int32_t B;
     int32_t nstrips, nbands, rows;  // tile grid of one frame
     int32_t ntiles;                 // B * nbands * nstrips
@@ -129,6 +133,6 @@ enum { KIND_F32 = 0, KIND_U16 = 1, KIND_F16 = 2, KIND_DISP = 3 };
 constexpr int kLenientFlag = 0x100;  // ORed into a kind: the lenient rule
 inline constexpr int base_kind(int kind) { return kind & ~kLenientFlag; }
 enum { AGG_MEAN = 0, AGG_MEDIAN = 1 };
-enum { OUT_F32 = 0, OUT_F16 = 1 };
+enum { OUT_F32 = 0, OUT_F16 = 1, OUT_RGBN = 2 };
 
 }  // namespace sne

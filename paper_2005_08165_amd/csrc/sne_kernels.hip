@@ -77,6 +77,11 @@
 #define SNE_BATCH_OCCUPANCY
 #endif
 
+// Packed output stores: 1 = ordinary (cached) stores, 0 = nontemporal.
+#ifndef SNE_RGBN_TEMPORAL
+#define SNE_RGBN_TEMPORAL 0
+#endif
+
 // Rows whose loads are in flight while a row is computed (1 or 2).
 #ifndef SNE_PREFETCH_ROWS
 #define SNE_PREFETCH_ROWS 1
@@ -362,6 +367,7 @@ template <> struct Out<OUT_F32> {
     using T = float;
     __device__ static T cvt(float x) { return x; }
 };
+template <> struct Out<OUT_RGBN>;  // FP16 channels, stored by tile_row's packed branch
 template <> struct Out<OUT_F16> {
     using T = _Float16;
     // Round the FP32 value to nearest even.  The value is pinned first so
@@ -374,6 +380,8 @@ template <> struct Out<OUT_F16> {
         return (_Float16)x;
     }
 };
+
+template <> struct Out<OUT_RGBN> : Out<OUT_F16> {};
 
 template <int PX> struct MaskWord;
 template <> struct MaskWord<1> { using T = uint8_t; };
@@ -539,13 +547,20 @@ __device__ __forceinline__ float lenient_combine(float c, bool hc, float a, bool
 // raw loads of row r + 1 on entry and those of row r + 1 + SNE_PREFETCH_ROWS
 // on exit.
 template <int KIND, bool FD, int AGG, int OUT, int PX, bool HALF, bool LEN>
-__device__ __forceinline__ void tile_row(const FrameDesc &f, const InBuf &ib, int r, int rend,
-                                         int col, int col_off, int halo_off, const Edges &e,
-                                         const GradW &gw, RawRow<KIND, PX> &pend,
+__device__ __forceinline__ void tile_row(const FrameDesc &f, const InBuf &ib, const InBuf &rgbb,
+                                         int r, int rend, int col, int col_off, int halo_off,
+                                         const Edges &e, const GradW &gw, RawRow<KIND, PX> &pend,
                                          const RowState<PX> &prev, RowState<PX> &cur,
                                          RowState<PX> &next) {
     finish_row<KIND, PX, HALF>(pend, next.row, e);
     load_raw<KIND, PX>(ib, r + 1 + SNE_PREFETCH_ROWS, col_off, halo_off, pend);  // prefetch
+    // packed output: this row's RGBX bytes, in flight while the row is
+    // computed (a frame without colour has an empty resource: zeros)
+    Vec<float, PX> rgbx;
+    if constexpr (OUT == OUT_RGBN)
+        rgbx = buf_load<float, PX>(
+            rgbb, (int)((unsigned)r * (unsigned)rgbb.pitch_bytes + (unsigned)(col_off < kOOB
+                                                                             ? col * 4 : kOOB)));
     make_pairs<PX>(cur.row, next.row, cur.below);
     const Row<PX> &rp = prev.row, &rc = cur.row, &rn = next.row;
     const Pairs<PX> &pu = prev.below, &pd = cur.below;
@@ -648,7 +663,35 @@ __device__ __forceinline__ void tile_row(const FrameDesc &f, const InBuf &ib, in
         oz.v[k] = Out<OUT>::cvt(keep ? nz * inv : (valid ? -1.f : 0.f));
         mk[k] = valid ? 1 : 0;
     }
-    if (col < f.W && r < rend) {
+    if constexpr (OUT == OUT_RGBN) {
+        // one 16-byte pixel: R, G, B (bytes / 255), mask, n_x, n_y, n_z, 0
+        if (col < f.W && r < rend) {
+            char *o = static_cast<char *>(f.out) +
+                      ((unsigned)r * (unsigned)f.out_pitch + (unsigned)col) * 16u;
+#pragma unroll
+            for (int k = 0; k < PX; ++k) {
+                const unsigned c = __builtin_bit_cast(unsigned, rgbx.v[k]);
+                const float s255 = 1.f / 255.f;
+                const _Float16 R = Out<OUT_F16>::cvt((float)(c & 0xffu) * s255);
+                const _Float16 G = Out<OUT_F16>::cvt((float)((c >> 8) & 0xffu) * s255);
+                const _Float16 Bc = Out<OUT_F16>::cvt((float)((c >> 16) & 0xffu) * s255);
+                const _Float16 M = mk[k] ? (_Float16)1.f : (_Float16)0.f;
+                typedef _Float16 H8 __attribute__((ext_vector_type(8)));
+                const H8 px = {R, G, Bc, M, ox.v[k], oy.v[k], oz.v[k], (_Float16)0.f};
+#if SNE_RGBN_TEMPORAL
+                *reinterpret_cast<H8 *>(o + 16 * k) = px;
+#else
+                store_stream(o + 16 * k, px);
+#endif
+            }
+            if (f.mask) {
+                typename MaskWord<PX>::T w = 0;
+#pragma unroll
+                for (int k = 0; k < PX; ++k) w |= (typename MaskWord<PX>::T)mk[k] << (8 * k);
+                store_stream(f.mask + ((unsigned)r * (unsigned)f.mask_pitch + (unsigned)col), w);
+            }
+        }
+    } else if (col < f.W && r < rend) {
         // uniform plane bases + one 32-bit byte offset per lane (the host
         // keeps each plane below 4 GiB)
         char *o = static_cast<char *>(f.out);
@@ -682,6 +725,8 @@ __device__ __forceinline__ void run_tile(const FrameDesc &f, int c0, int r0, int
     const int col = c0 + llane * PX;
     const int esz = (int)sizeof(T);
     const InBuf ib = make_inbuf(f.in, f.in_pitch, f.H, esz);
+    InBuf rgbb{};
+    if constexpr (OUT == OUT_RGBN) rgbb = make_inbuf(f.rgb, f.rgb ? f.rgb_pitch : 0, f.H, 1);
     const int col_off = col < f.W ? col * esz : kOOB;
     int hcol = -1;
     if (llane == 0) hcol = c0 - 1;
@@ -700,9 +745,9 @@ __device__ __forceinline__ void run_tile(const FrameDesc &f, int c0, int r0, int
     finish_row<KIND, PX, HALF>(p0, B.row, e);
     make_pairs<PX>(A.row, B.row, A.below);
     load_raw<KIND, PX>(ib, rb + 1, col_off, halo_off, p0);
-#define SNE_ROW(I, P, X, Y, Z)                                                                 \
-    tile_row<KIND, FD, AGG, OUT, PX, HALF, LEN>(f, ib, rb + (I), rend, col, col_off, halo_off, e, \
-                                                gw, P, X, Y, Z)
+#define SNE_ROW(I, P, X, Y, Z)                                                                  \
+    tile_row<KIND, FD, AGG, OUT, PX, HALF, LEN>(f, ib, rgbb, rb + (I), rend, col, col_off, halo_off, \
+                                                e, gw, P, X, Y, Z)
 #if SNE_PREFETCH_ROWS == 1
     for (int i = 0; i < n; i += 3) {
         SNE_ROW(i, p0, A, B, C);
@@ -757,6 +802,8 @@ __global__ __launch_bounds__(kBlock) SNE_OCCUPANCY void sne_uniform_kernel(Unifo
     f.in = static_cast<const IT *>(a.f.in) + frame * a.in_fstride;
     f.out = static_cast<OT *>(a.f.out) + frame * a.out_fstride;
     if (f.mask) f.mask = a.f.mask + frame * a.mask_fstride;
+    if constexpr (OUT == OUT_RGBN)
+        if (f.rgb) f.rgb = static_cast<const char *>(a.f.rgb) + frame * a.rgb_fstride;
     // half-wave mode: a "band" is a pair of bands and a strip is 32 PX wide
     const int r0 = band * a.rows * (HALF ? 2 : 1);
     run_tile<KIND, FD, AGG, OUT, PX, HALF, LEN>(f, strip * (HALF ? kWave / 2 : kWave) * PX, r0,
@@ -915,8 +962,15 @@ hipError_t occupancy_px(int px, int *blocks) {
     ((v).grad == 0 ? SNE_DISPATCH_AGG(FN, KIND, true, v, __VA_ARGS__)                      \
                    : SNE_DISPATCH_AGG(FN, KIND, false, v, __VA_ARGS__))
 
+#define SNE_DISPATCH_RGBN_AGG(FN, KIND, FD, v, ...)                                        \
+    ((v).agg == AGG_MEAN ? SNE_DISPATCH_LEN(FN, KIND, FD, AGG_MEAN, OUT_RGBN, v, __VA_ARGS__)  \
+                         : SNE_DISPATCH_LEN(FN, KIND, FD, AGG_MEDIAN, OUT_RGBN, v, __VA_ARGS__))
+
 template <int KIND>
 hipError_t uniform_variant(const Variant &v, const UniformArgs &a, int grid, hipStream_t s) {
+    if (v.out == OUT_RGBN)  // the packed output exists for single frames and uniform batches
+        return (v.grad == 0 ? SNE_DISPATCH_RGBN_AGG(uniform_px, KIND, true, v, a, grid, s)
+                            : SNE_DISPATCH_RGBN_AGG(uniform_px, KIND, false, v, a, grid, s));
     return SNE_DISPATCH(uniform_px, KIND, v, a, grid, s);
 }
 template <int KIND>

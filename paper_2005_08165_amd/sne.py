@@ -131,6 +131,9 @@ _SIGS = {
     "sne_estimate_uniform": ([_vp, _vp, _i32, _i32, _i32, _i64, _i64, ctypes.POINTER(Intrinsics),
                               _int, _int, _int, _int, _vp, _i64, _i64, _vp, _i64, _i64, _vp],
                              _int),
+    "sne_estimate_rgbn": ([_vp, _vp, _i32, _i32, _i32, _i64, _i64, ctypes.POINTER(Intrinsics),
+                           _int, _int, _int, _vp, _i64, _i64, _vp, _i64, _i64, _vp, _i64, _i64,
+                           _vp], _int),
     "sne_set_intrinsics_table": ([_vp, ctypes.POINTER(Intrinsics), _i32], _int),
     "sne_estimate_batched": ([_vp, ctypes.POINTER(FrameDesc), _i32, _int, _int, _int, _int, _vp],
                              _int),
@@ -626,6 +629,45 @@ def estimate_uniform(raw: torch.Tensor, K, kind="depth_f32", grad="fd", agg="mea
         0 if mask is None else mask.stride(0), _stream(stream))
     check("sne_estimate_uniform", st)
     return normals, mask
+
+
+def estimate_rgbn(raw: torch.Tensor, K, kind="depth_f32", grad="fd", agg="mean",
+                  rgb: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
+                  mask: Optional[torch.Tensor] = None, stream=None,
+                  ctx: Optional[Context] = None) -> torch.Tensor:
+    """sne_estimate_rgbn on [B, H, W] depth (or [H, W]): returns the packed
+    [B, H, W, 8] FP16 tensor (R, G, B, mask, n_x, n_y, n_z, 0); rgb is a
+    [B, H, W, 4] uint8 RGBX tensor or None."""
+    kind_i = _kind(kind)
+    single = raw.dim() == 2
+    if single:
+        raw = raw.unsqueeze(0)
+        rgb = None if rgb is None else rgb.unsqueeze(0)
+        mask = None if mask is None else mask.unsqueeze(0)
+    if raw.dim() != 3:
+        raise ValueError("expected [B, H, W] or [H, W]")
+    if raw.dtype != _dtype(kind_i):
+        raise TypeError("kind %s needs %s input" % (kind, _dtype(kind_i)))
+    B, H, W = raw.shape
+    if rgb is not None and (tuple(rgb.shape) != (B, H, W, 4) or rgb.dtype != torch.uint8 or
+                            rgb.stride(-1) != 1 or rgb.stride(-2) != 4):
+        raise ValueError("rgb must be a [B, H, W, 4] uint8 tensor with packed pixels")
+    if out is None:
+        out = torch.empty((B, H, W, 8), dtype=torch.float16, device=raw.device)
+    if (tuple(out.shape) != (B, H, W, 8) or out.dtype != torch.float16 or out.stride(-1) != 1
+            or out.stride(-2) != 8):
+        raise ValueError("out must be a [B, H, W, 8] float16 tensor with packed pixels")
+    _on_gpu(raw, rgb, out, mask)
+    Kc = _K(K)
+    st = lib().sne_estimate_rgbn(
+        None if ctx is None else ctx.handle, raw.data_ptr(), B, H, W, _row_pitch(raw),
+        raw.stride(0), ctypes.byref(Kc), kind_i, _enum(GRAD, grad, "grad"),
+        _enum(AGG, agg, "agg"), _ptr(rgb), 0 if rgb is None else rgb.stride(1),
+        0 if rgb is None else rgb.stride(0), out.data_ptr(), out.stride(1) // 8,
+        out.stride(0) // 8, _ptr(mask), 0 if mask is None else _row_pitch(mask),
+        0 if mask is None else mask.stride(0), _stream(stream))
+    check("sne_estimate_rgbn", st)
+    return out[0] if single else out
 
 
 def status_string(code: int) -> str:

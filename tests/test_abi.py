@@ -218,3 +218,16 @@ def test_lenient_kind_suffix():
     assert sne._kind("disparity_f32") == 3
     with pytest.raises(ValueError):
         sne._kind("depth_u16+loose")
+
+
+def test_rgbn_argument_errors():
+    L = sne.lib()
+    K = _K()
+    good = dict(ctx=None, inp=FAKE, B=1, H=8, W=8, in_pitch=8, in_fs=0, K=ctypes.byref(K), kind=0,
+                grad=0, agg=0, rgb=None, rgb_pitch=0, rgb_fs=0, out=FAKE, out_pitch=8, out_fs=0,
+                mask=None, mask_pitch=0, mask_fs=0, stream=None)
+    for bad in [dict(out=FAKE + 8), dict(rgb=FAKE, rgb_pitch=16), dict(rgb=FAKE, rgb_pitch=34),
+                dict(rgb=FAKE + 2, rgb_pitch=32), dict(out_pitch=4), dict(kind=9), dict(inp=None),
+                dict(B=2, out_fs=63)]:
+        a = dict(good, **bad)
+        assert L.sne_estimate_rgbn(*a.values()) == sne.SNE_ERR_ARG, bad
