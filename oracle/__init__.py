@@ -54,7 +54,7 @@ def _load():
         dp = ctypes.POINTER(ctypes.c_double)
         common = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
                   ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                  ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+                  ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
         lib.orc_estimate.argtypes = common + [dp, ctypes.c_void_p, dp, ctypes.c_void_p,
                                               ctypes.c_int]
         lib.orc_estimate.restype = ctypes.c_int
@@ -82,14 +82,25 @@ def _prep(raw: np.ndarray, kind: str) -> np.ndarray:
     return raw
 
 
-def estimate(raw: np.ndarray, kind: str, K: Sequence[float], grad: str = "fd",
+def _grad(grad):
+    """(code, kx) of a gradient filter: a name, or a 3x3 K_x (custom)."""
+    if isinstance(grad, str):
+        return GRADS[grad], None
+    kx = np.ascontiguousarray(np.asarray(grad, dtype=np.float64))
+    if kx.shape != (3, 3):
+        raise ValueError("a custom gradient kernel is 3x3")
+    return 4, kx
+
+
+def estimate(raw: np.ndarray, kind: str, K: Sequence[float], grad="fd",
              agg: str = "mean", tc: float = 1.0, threads: int = 0, unnorm: bool = False,
              mcount: bool = False, rule: str = "strict"):
     """Normals [3,H,W] float64 and mask [H,W] uint8 of one image.
 
     ``rule``: "strict" (a fully valid 3x3 window at an interior pixel) or
     "lenient" (valid neighbours only, one-sided gradient lines; see the header
-    of sne_oracle.c).
+    of sne_oracle.c).  ``grad``: "fd", "sobel", "scharr", "prewitt" or a 3x3
+    custom K_x (row-major, K_y = K_x^T).
 
     K = (fx, fy, u0, v0) as the values the caller wants used (pass the FP32
     values a GPU run used to compare like with like).  With ``unnorm`` the
@@ -102,8 +113,9 @@ def estimate(raw: np.ndarray, kind: str, K: Sequence[float], grad: str = "fd",
     msk = np.zeros((H, W), np.uint8)
     un = np.zeros((3, H, W), np.float64) if unnorm else None
     mc = np.zeros((H, W), np.int32) if mcount else None
+    g, kx = _grad(grad)
     rc = _load().orc_estimate(raw.ctypes.data, KINDS[kind], H, W, W, fx, fy, u0, v0, float(tc),
-                              GRADS[grad], AGGS[agg], RULES[rule], _dp(nrm), msk.ctypes.data,
+                              g, AGGS[agg], RULES[rule], _dp(kx), _dp(nrm), msk.ctypes.data,
                               _dp(un),
                               None if mc is None else mc.ctypes.data, int(threads))
     if rc != 0:
@@ -117,7 +129,7 @@ def estimate(raw: np.ndarray, kind: str, K: Sequence[float], grad: str = "fd",
 
 
 def estimate_pixels(raw: np.ndarray, kind: str, K: Sequence[float], pix: np.ndarray,
-                    grad: str = "fd", agg: str = "mean", tc: float = 1.0, threads: int = 0,
+                    grad="fd", agg: str = "mean", tc: float = 1.0, threads: int = 0,
                     unnorm: bool = False, mcount: bool = False, rule: str = "strict"):
     """Normals [n,3] and mask [n] at flat pixel indices ``pix`` (v*W + u)."""
     raw = _prep(raw, kind)
@@ -129,8 +141,9 @@ def estimate_pixels(raw: np.ndarray, kind: str, K: Sequence[float], pix: np.ndar
     msk = np.zeros(n, np.uint8)
     un = np.zeros((n, 3), np.float64) if unnorm else None
     mc = np.zeros(n, np.int32) if mcount else None
+    g, kx = _grad(grad)
     rc = _load().orc_estimate_pixels(raw.ctypes.data, KINDS[kind], H, W, W, fx, fy, u0, v0,
-                                     float(tc), GRADS[grad], AGGS[agg], RULES[rule],
+                                     float(tc), g, AGGS[agg], RULES[rule], _dp(kx),
                                      pix.ctypes.data, n,
                                      _dp(nrm), msk.ctypes.data, _dp(un),
                                      None if mc is None else mc.ctypes.data, int(threads))

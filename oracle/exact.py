@@ -32,7 +32,8 @@ def _median(vals):
 def pixel(img, v, u, K, grad="fd", agg="mean", disparity=False, tc=1, rule="strict"):
     """Return (mask, nprime or None, normal tuple of floats) for pixel (v, u).
 
-    img: list of rows of ints (0 = invalid); K = (fx, fy, u0, v0) rationals.
+    img: list of rows of ints (0 = invalid); K = (fx, fy, u0, v0) rationals;
+    grad: a kernel name or a 3x3 K_x of rationals (custom, K_y = K_x^T).
     rule "lenient": the reading for holes and borders stated in the header of
     sne_oracle.c, restated by pixel_lenient below."""
     if rule == "lenient":
@@ -50,7 +51,7 @@ def pixel(img, v, u, K, grad="fd", agg="mean", disparity=False, tc=1, rule="stri
     # depth and the filtered image
     z = [[(fx * Fr(tc) / Fr(x)) if disparity else Fr(x) for x in row] for row in win]
     s = [[Fr(win[a][b]) if disparity else 1 / z[a][b] for b in range(3)] for a in range(3)]
-    k = KX[grad]
+    k = KX[grad] if isinstance(grad, str) else [[Fr(x) for x in row] for row in grad]
     Gu = sum(k[a][b] * s[a][b] for a in range(3) for b in range(3))
     Gv = sum(k[b][a] * s[a][b] for a in range(3) for b in range(3))
     nx = Gu if disparity else fx * Gu

@@ -73,6 +73,13 @@
  *   - A pixel whose valid neighbours all carry its raw value gets (0, 0, -1).
  * On a window whose 9 samples are valid this is the strict definition (up to
  * the order of the additions in the gradient lines).
+ *
+ * Custom gradient kernel (grad = 4).  The paper compares the four kernels
+ * and searches 3x3 kernel weights by brute force (Sec. IV-B, Fig. 2): any
+ * 3x3 K_x (K_y = K_x^T) can be passed as kx[9], row-major, rows v-1..v+1 and
+ * columns u-1..u+1; step 5 then sums K_x[a][b] s(v+a-1, u+b-1) row by row
+ * (and K_y column by column) exactly as for the built-in kernels.  The
+ * lenient rule is defined for the built-in kernels only.
  */
 #include <math.h>
 #include <stddef.h>
@@ -88,7 +95,7 @@
 
 enum { K_DEPTH_F32 = 0, K_DEPTH_U16 = 1, K_DEPTH_F16 = 2, K_DISP_F32 = 3,
        K_DEPTH_F64 = 4, K_DISP_F64 = 5 };
-enum { G_FD = 0, G_SOBEL = 1, G_SCHARR = 2, G_PREWITT = 3 };
+enum { G_FD = 0, G_SOBEL = 1, G_SCHARR = 2, G_PREWITT = 3, G_CUSTOM = 4 };
 enum { A_MEAN = 0, A_MEDIAN = 1 };
 
 /* Horizontal-derivative kernels K_x[row][col]; row/col index = offset + 1. */
@@ -105,7 +112,13 @@ typedef struct {
     int64_t pitch;               /* elements between rows */
     double fx, fy, u0, v0, tc;
     int grad, agg, rule;
+    const double *kx;            /* grad = G_CUSTOM: K_x row-major */
 } orc_img;
+
+/* The horizontal-derivative kernel of the image's gradient filter. */
+static const double (*kernel_of(const orc_img *im))[3] {
+    return im->grad == G_CUSTOM ? (const double (*)[3])im->kx : KX[im->grad];
+}
 
 /* IEEE binary16 -> double, from the format's definition. */
 static double half_bits_to_double(uint16_t h) {
@@ -176,7 +189,7 @@ static void pixel(const orc_img *im, int v, int u, double out[3], unsigned char 
         }
 
     /* Filters 1 and 2: correlation with K_x and K_y = K_x^T, line by line. */
-    const double (*K)[3] = KX[im->grad];
+    const double (*K)[3] = kernel_of(im);
     double Gu = 0.0, Gv = 0.0;
     for (int a = 0; a < 3; ++a) {          /* rows of K_x */
         double line = 0.0;
@@ -383,10 +396,12 @@ static void eval_pixel(const orc_img *im, int v, int u, double out[3], unsigned 
 }
 
 static int check_args(const void *raw, int kind, int H, int W, int64_t pitch, double fx,
-                      double fy, int grad, int agg) {
+                      double fy, int grad, int agg, int rule, const double *kx) {
     if (!raw || H < 1 || W < 1 || pitch < W) return ORC_EARG;
     if (kind < K_DEPTH_F32 || kind > K_DISP_F64) return ORC_EARG;
-    if (grad < G_FD || grad > G_PREWITT || agg < A_MEAN || agg > A_MEDIAN) return ORC_EARG;
+    if (grad < G_FD || grad > G_CUSTOM || agg < A_MEAN || agg > A_MEDIAN) return ORC_EARG;
+    if (rule != 0 && rule != 1) return ORC_EARG;
+    if ((grad == G_CUSTOM) != (kx != NULL) || (grad == G_CUSTOM && rule == 1)) return ORC_EARG;
     if (!(fx > 0.0) || !(fy > 0.0)) return ORC_EARG;
     if (is_disparity(kind) && fx != fy) return ORC_EARG;
     return ORC_OK;
@@ -396,12 +411,13 @@ static int check_args(const void *raw, int kind, int H, int W, int64_t pitch, do
  * unnorm: optional [3][H][W]; mcount: optional [H][W] int (candidates kept,
  * -1 masked).  nthreads <= 0 uses the OpenMP default. */
 int orc_estimate(const void *raw, int kind, int H, int W, int64_t pitch, double fx, double fy,
-                 double u0, double v0, double tc, int grad, int agg, int rule, double *normals,
-                 unsigned char *mask, double *unnorm, int *mcount, int nthreads) {
-    if (check_args(raw, kind, H, W, pitch, fx, fy, grad, agg) != ORC_OK || !normals || !mask ||
-        (rule != 0 && rule != 1))
+                 double u0, double v0, double tc, int grad, int agg, int rule, const double *kx,
+                 double *normals, unsigned char *mask, double *unnorm, int *mcount,
+                 int nthreads) {
+    if (check_args(raw, kind, H, W, pitch, fx, fy, grad, agg, rule, kx) != ORC_OK || !normals ||
+        !mask)
         return ORC_EARG;
-    orc_img im = {raw, kind, H, W, pitch, fx, fy, u0, v0, tc, grad, agg, rule};
+    orc_img im = {raw, kind, H, W, pitch, fx, fy, u0, v0, tc, grad, agg, rule, kx};
     const int64_t plane = (int64_t)H * W;
 #ifdef _OPENMP
     if (nthreads <= 0) nthreads = omp_get_max_threads();
@@ -432,14 +448,14 @@ int orc_estimate(const void *raw, int kind, int H, int W, int64_t pitch, double 
  * unnorm optional [n][3]; mcount optional [n]. */
 int orc_estimate_pixels(const void *raw, int kind, int H, int W, int64_t pitch, double fx,
                         double fy, double u0, double v0, double tc, int grad, int agg, int rule,
-                        const int64_t *pix, int64_t n, double *normals, unsigned char *mask,
-                        double *unnorm, int *mcount, int nthreads) {
-    if (check_args(raw, kind, H, W, pitch, fx, fy, grad, agg) != ORC_OK || !pix || !normals ||
-        !mask || n < 0 || (rule != 0 && rule != 1))
+                        const double *kx, const int64_t *pix, int64_t n, double *normals,
+                        unsigned char *mask, double *unnorm, int *mcount, int nthreads) {
+    if (check_args(raw, kind, H, W, pitch, fx, fy, grad, agg, rule, kx) != ORC_OK || !pix ||
+        !normals || !mask || n < 0)
         return ORC_EARG;
     for (int64_t k = 0; k < n; ++k)
         if (pix[k] < 0 || pix[k] >= (int64_t)H * W) return ORC_EARG;
-    orc_img im = {raw, kind, H, W, pitch, fx, fy, u0, v0, tc, grad, agg, rule};
+    orc_img im = {raw, kind, H, W, pitch, fx, fy, u0, v0, tc, grad, agg, rule, kx};
 #ifdef _OPENMP
     if (nthreads <= 0) nthreads = omp_get_max_threads();
 #pragma omp parallel for schedule(static) num_threads(nthreads)

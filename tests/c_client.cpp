@@ -17,8 +17,8 @@
 
 extern "C" int orc_estimate(const void *raw, int kind, int H, int W, int64_t pitch, double fx,
                             double fy, double u0, double v0, double tc, int grad, int agg,
-                            int rule, double *normals, unsigned char *mask, double *unnorm,
-                            int *mcount, int nthreads);
+                            int rule, const double *kx, double *normals, unsigned char *mask,
+                            double *unnorm, int *mcount, int nthreads);
 
 #define CHECK(c)                                                              \
     do {                                                                      \
@@ -110,7 +110,8 @@ int main() {
         std::vector<double> on(3 * (size_t)H * W);
         std::vector<unsigned char> om((size_t)H * W);
         CHECK(orc_estimate(z.data(), 0, H, W, W, K.fx, K.fy, K.u0, K.v0, 1.0, SNE_GRAD_SOBEL,
-                           SNE_AGG_MEDIAN, rule, on.data(), om.data(), nullptr, nullptr, 0) == 0);
+                           SNE_AGG_MEDIAN, rule, nullptr, on.data(), om.data(), nullptr, nullptr,
+                           0) == 0);
         double sum = 0, mx = 0;
         size_t nvalid = 0;
         const size_t P = (size_t)H * W;

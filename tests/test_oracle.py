@@ -603,3 +603,70 @@ def test_lenient_mask_rules():
     # constant image: every kept pixel is degenerate
     n, m = oracle.estimate(img, "depth_u16", K, "sobel", "median", rule="lenient")
     assert m.all() and (n[2] == -1).all() and (n[:2] == 0).all()
+
+
+# --------------------------------------------------------------------------
+# custom 3x3 gradient kernels (the paper's kernel search, Sec. IV-B)
+# --------------------------------------------------------------------------
+
+BUILTIN_KX = {"fd": [[0, 0, 0], [-1, 0, 1], [0, 0, 0]],
+              "sobel": [[-1, 0, 1], [-2, 0, 2], [-1, 0, 1]],
+              "scharr": [[-3, 0, 3], [-10, 0, 10], [-3, 0, 3]],
+              "prewitt": [[-1, 0, 1], [-1, 0, 1], [-1, 0, 1]]}
+
+
+@pytest.mark.parametrize("agg", AGGS)
+def test_custom_kernel_reproduces_the_named_ones(agg):
+    """Passing a named kernel's weights as a custom kernel is the same
+    computation (bit for bit in FP64); scaling the kernel leaves the normals
+    unchanged (reading R3)."""
+    fr = S.make_cluttered(91, S.Camera(50, 70, 50.2, 50.2, 34.5, 24.5))
+    raw, K = fr.raw.numpy(), fr.cam.as_tuple()
+    for name, kx in BUILTIN_KX.items():
+        n0, m0 = oracle.estimate(raw, "depth_f32", K, name, agg)
+        n1, m1 = oracle.estimate(raw, "depth_f32", K, kx, agg)
+        assert (m0 == m1).all() and np.array_equal(n0, n1), name
+        n2, _ = oracle.estimate(raw, "depth_f32", K, 2.75 * np.array(kx, float), agg)
+        np.testing.assert_allclose(n2, n0, atol=1e-12)
+
+
+@pytest.mark.parametrize("agg", AGGS)
+def test_custom_derivative_kernels_exact_on_planes(agg):
+    """Any K_x whose rows are w_a [-1 0 1] (w_a >= 0, not all 0; unequal
+    rows allowed) differentiates an affine s exactly in u, and K_y = K_x^T in
+    v with the same factor 2 sum(w): plane normals are exact."""
+    rng = np.random.default_rng(17)
+    H, W, K = 30, 40, (45.0, 47.0, 19.5, 14.5)
+    for n, b in _random_planes(23, 3, H, W, K):
+        z = _plane_depth(n, b, H, W, K)
+        w = rng.uniform(0.0, 3.0, size=3)
+        kx = np.array([[-w[0], 0, w[0]], [-w[1], 0, w[1]], [-w[2], 0, w[2]]])
+        nrm, msk, un = oracle.estimate(z, "depth_f64", K, kx, agg, unnorm=True)
+        m = msk.astype(bool)
+        err = oracle.angular_error_deg(nrm, np.broadcast_to(n[:, None, None], nrm.shape))[m]
+        assert err.max() < 1e-8
+        dot = (un * _backproject(z, K)).sum(0)[m]
+        np.testing.assert_allclose(dot, 2.0 * w.sum(), rtol=1e-9)
+
+
+@pytest.mark.parametrize("agg", AGGS)
+def test_custom_kernels_bruteforce_exact(agg):
+    """Arbitrary integer 3x3 kernels (no symmetry, non-zero row sums
+    included) against the rational brute force on small integer images."""
+    rng = np.random.default_rng(29)
+    Kc = (2.5, 3.0, 3.5, 3.25)
+    for t in range(6):
+        kx = rng.integers(-4, 5, size=(3, 3))
+        for img in _tiny_images(500 + t, 2):
+            mask_x, _, nrm_x = exact.image(img.tolist(), Kc, kx.tolist(), agg)
+            nrm, msk = oracle.estimate(img.astype(np.uint16), "depth_u16", Kc, kx, agg)
+            assert (np.array(mask_x) == msk).all()
+            np.testing.assert_allclose(nrm, np.moveaxis(np.array(nrm_x), -1, 0), atol=1e-12)
+
+
+def test_custom_kernel_argument_rules():
+    raw = np.full((5, 5), 2.0, np.float32)
+    with pytest.raises(ValueError):
+        oracle.estimate(raw, "depth_f32", (5, 5, 2, 2), np.ones((2, 3)), "mean")
+    with pytest.raises(ValueError):  # the lenient rule is defined for the named kernels only
+        oracle.estimate(raw, "depth_f32", (5, 5, 2, 2), np.ones((3, 3)), "mean", rule="lenient")
