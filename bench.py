@@ -427,6 +427,7 @@ def main():
     ap.add_argument("--no-disparity", action="store_true")
     ap.add_argument("--no-lenient", action="store_true")
     ap.add_argument("--no-packed", action="store_true")
+    ap.add_argument("--no-custom", action="store_true")
     ap.add_argument("--disparity-steps", type=int, default=300)
     ap.add_argument("--serving-rate", type=float, default=0.0,
                     help="run the serving loop at this one offered rate (FD-mean) only")
@@ -524,6 +525,27 @@ def main():
                     "one-sided difference, invalid neighbours leave filter 3",
             "us_per_launch": round(ev_l / lsteps * 1e6, 2),
             "mpix_per_s": round(px * lsteps / ev_l / 1e6, 1),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                         "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                         "algorithmic_bytes_per_launch": bytes_per_launch}}
+    if not args.no_custom:
+        log("custom 3x3 gradient kernel on the same batches")
+        cctx = sne.Context(0)
+        cctx.set_gradient_kernel([[-1.0, 0.0, 1.0], [-3.0, 0.0, 3.0], [-1.0, 0.0, 1.0]])
+
+        def step_cus(i):
+            raw, nrm, msk = bufs[i % NBUF]
+            sne.estimate_uniform(raw, K, "depth_f32", "custom", args.agg, normals=nrm, mask=msk,
+                                 ctx=cctx)
+
+        csteps = max(args.steps // 3, 10)
+        wall_c, ev_c = time_launches(torch, step_cus, max(args.warmup // 3, 5), csteps)
+        gbs = bytes_per_launch / (ev_c / csteps) / 1e9
+        res["custom_kernel_batch"] = {
+            "workload": "batch64_480x640_f32depth_custom3x3_%s" % args.agg,
+            "kernel": "K_x rows [-1 0 1], [-3 0 3], [-1 0 1] given as weights",
+            "us_per_launch": round(ev_c / csteps * 1e6, 2),
+            "mpix_per_s": round(px * csteps / ev_c / 1e6, 1),
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
                          "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
                          "algorithmic_bytes_per_launch": bytes_per_launch}}

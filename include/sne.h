@@ -94,6 +94,12 @@ typedef struct {
 #define SNE_GRAD_SOBEL 1
 #define SNE_GRAD_SCHARR 2
 #define SNE_GRAD_PREWITT 3
+/* Any 3x3 K_x (K_y = K_x^T), set on the context with
+ * sne_set_gradient_kernel: the paper searches 3x3 kernel weights by brute
+ * force (Sec. IV-B).  Single frames and uniform batches (sne_estimate,
+ * sne_estimate_uniform) with a context, strict rule only; other calls return
+ * SNE_ERR_UNSUPPORTED. */
+#define SNE_GRAD_CUSTOM 4
 
 /* Filter 3 (Phi of eq. nx2_ny2_nz2). */
 #define SNE_AGG_MEAN 0
@@ -153,6 +159,14 @@ int sne_estimate_rgbn(sne_ctx *ctx, const void *in, int32_t B, int32_t H, int32_
                       int64_t rgb_frame_stride, void *out, int64_t out_pitch,
                       int64_t out_frame_stride, uint8_t *mask, int64_t mask_pitch,
                       int64_t mask_frame_stride, void *stream);
+
+/* Set the context's custom gradient kernel: kx[9] is K_x row-major (rows
+ * v-1, v, v+1; columns u-1, u, u+1), finite; K_y = K_x^T.  Calls with
+ * grad = SNE_GRAD_CUSTOM on ctx use it; SNE_ERR_STATE from such a call
+ * before one was set.  Each line of K_x is evaluated as
+ * K[a][2] (s_+ - s_0) - K[a][0] (s_0 - s_-) + (K[a][0] + K[a][1] + K[a][2]) s_0
+ * with the differences of 1/z formed from raw-value differences. */
+int sne_set_gradient_kernel(sne_ctx *ctx, const float kx[9]);
 
 /* Descriptor of one frame of an uneven batch (all device pointers). */
 typedef struct {

@@ -49,6 +49,16 @@ size_t out_elem(int out) { return out == SNE_OUT_F32 ? 4 : 2; }
 // 3:10, Prewitt 1:1.  FD uses the centre row only.  The lenient rule's
 // rescaling factors are the full weight 1 + 2 wa over the available weight
 // (1 + wa, 1, 2 wa, wa), rounded once from double.
+// A custom K_x as the kernels take it: per line the outer weights and the
+// line's sum (added in double, rounded once).
+void custom_weights(const float kx[9], GradW &w) {
+    for (int a = 0; a < 3; ++a) {
+        w.k0[a] = kx[3 * a];
+        w.k2[a] = kx[3 * a + 2];
+        w.ks[a] = (float)((double)kx[3 * a] + (double)kx[3 * a + 1] + (double)kx[3 * a + 2]);
+    }
+}
+
 void grad_weights(int grad, GradW &w) {
     double a = 0.0;
     switch (grad) {
@@ -63,6 +73,7 @@ void grad_weights(int grad, GradW &w) {
     w.r[1] = (float)full;
     w.r[2] = a > 0.0 ? (float)(full / (2.0 * a)) : 0.f;
     w.r[3] = a > 0.0 ? (float)(full / a) : 0.f;
+    for (int i = 0; i < 3; ++i) w.k0[i] = w.k2[i] = w.ks[i] = 0.f;
 }
 
 bool aligned(const void *p, size_t bytes) { return ((uintptr_t)p % bytes) == 0; }
@@ -243,9 +254,17 @@ int uniform_impl(sne_ctx *ctx, const void *in, int32_t B, int32_t H, int32_t W, 
                  int64_t mask_pitch, int64_t mask_fs, void *stream, const TileChoice *force,
                  const RgbArgs *rgb = nullptr) {
     const bool packed = rgb != nullptr;
-    if (!(packed ? valid_enum(kind, grad, agg, SNE_OUT_F32) : valid_enum(kind, grad, agg, out_type))
-        || !valid_K(K, kind))
+    const bool custom = grad == SNE_GRAD_CUSTOM;
+    const int grad_check = custom ? SNE_GRAD_FD : grad;
+    if (!(packed ? valid_enum(kind, grad_check, agg, SNE_OUT_F32)
+                 : valid_enum(kind, grad_check, agg, out_type)) ||
+        !valid_K(K, kind))
         return SNE_ERR_ARG;
+    if (custom) {
+        if (!ctx) return SNE_ERR_ARG;
+        if (packed || (kind & SNE_LENIENT)) return SNE_ERR_UNSUPPORTED;
+        if (!ctx->has_custom) return SNE_ERR_STATE;
+    }
     if (B < 0 || H < 1 || W < 1 || in_pitch < W || out_pitch < W) return SNE_ERR_ARG;
     if (mask && mask_pitch < W) return SNE_ERR_ARG;
     if (B == 0) return SNE_OK;  // an empty batch: the pointers may be NULL
@@ -303,6 +322,7 @@ int uniform_impl(sne_ctx *ctx, const void *in, int32_t B, int32_t H, int32_t W, 
     a.ntiles = (int32_t)ntiles;
     a.xcd_remap = t.remap;
     grad_weights(grad, a.gw);
+    if (custom) custom_weights(ctx->custom_kx, a.gw);
     const int grid = (int)((ntiles + kWavesPerBlock - 1) / kWavesPerBlock);
     if (ctx && hipSetDevice(ctx->device) != hipSuccess) return SNE_ERR_HIP;
     hipError_t e = launch_uniform(v, a, grid, (hipStream_t)stream);
@@ -384,6 +404,7 @@ int stage_and_launch(sne_ctx *ctx, const sne_frame *frames, int32_t n, const Var
 
 int batched_impl(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int grad, int agg,
                  int out_type, void *stream, const TileChoice *force) {
+    if (grad == SNE_GRAD_CUSTOM) return SNE_ERR_UNSUPPORTED;
     if (!ctx || n < 0 || !valid_enum(kind, grad, agg, out_type)) return SNE_ERR_ARG;
     if (n == 0) return SNE_OK;  // an empty batch: frames may be NULL
     if (!frames) return SNE_ERR_ARG;
@@ -626,6 +647,15 @@ int sne_estimate_uniform(sne_ctx *ctx, const void *in, int32_t B, int32_t H, int
                         stream, nullptr);
 }
 
+int sne_set_gradient_kernel(sne_ctx *ctx, const float kx[9]) {
+    if (!ctx || !kx) return SNE_ERR_ARG;
+    for (int i = 0; i < 9; ++i)
+        if (!std::isfinite(kx[i])) return SNE_ERR_ARG;
+    std::memcpy(ctx->custom_kx, kx, sizeof ctx->custom_kx);
+    ctx->has_custom = true;
+    return SNE_OK;
+}
+
 int sne_estimate_rgbn(sne_ctx *ctx, const void *in, int32_t B, int32_t H, int32_t W,
                       int64_t in_pitch, int64_t in_frame_stride, const sne_intrinsics *K,
                       int kind, int grad, int agg, const void *rgb, int64_t rgb_pitch,
@@ -674,6 +704,7 @@ int sne_estimate_batched(sne_ctx *ctx, const sne_frame *frames, int32_t n, int k
 
 int sne_estimate_batched_noalloc(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind,
                                  int grad, int agg, int out_type, void *stream) {
+    if (grad == SNE_GRAD_CUSTOM) return SNE_ERR_UNSUPPORTED;
     if (!ctx || n < 0 || !valid_enum(kind, grad, agg, out_type)) return SNE_ERR_ARG;
     if (n == 0) return SNE_OK;
     if (!frames) return SNE_ERR_ARG;
@@ -723,6 +754,7 @@ int sne_get_tile(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int gr
 
 int sne_autotune(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int grad, int agg,
                  int out_type, sne_tile *tile) {
+    if (grad == SNE_GRAD_CUSTOM) return SNE_ERR_UNSUPPORTED;
     if (!ctx || H < 1 || W < 1 || B < 1 || !valid_enum(kind, grad, agg, out_type))
         return SNE_ERR_ARG;
     if (hipSetDevice(ctx->device) != hipSuccess) return SNE_ERR_HIP;
@@ -790,6 +822,7 @@ int sne_autotune(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int gr
 
 int sne_autotune_batched(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int grad,
                          int agg, int out_type, sne_tile *tile) {
+    if (grad == SNE_GRAD_CUSTOM) return SNE_ERR_UNSUPPORTED;
     if (!ctx || n < 1 || !frames || !valid_enum(kind, grad, agg, out_type)) return SNE_ERR_ARG;
     int maxH = 0, maxW = 0, pxmax = 4;
     const int rc0 = scan_batch(ctx, frames, n, kind, out_type, maxH, maxW, pxmax);

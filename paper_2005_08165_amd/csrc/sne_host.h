@@ -130,6 +130,9 @@ struct sne_ctx {
     void *noalloc_table = nullptr;
     void *noalloc_stage = nullptr;
     hipEvent_t noalloc_copied = nullptr;
+    // SNE_GRAD_CUSTOM: K_x row-major, once set
+    bool has_custom = false;
+    float custom_kx[9] = {};
 };
 
 namespace sne {

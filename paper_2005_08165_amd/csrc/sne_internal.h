@@ -32,10 +32,20 @@ struct FrameDesc {
 // for the lenient rule the factors that rescale a sum of the available lines
 // to the full filter's weight 1 + 2 wa: r[0] the centre and one side line,
 // r[1] the centre line only, r[2] both side lines, r[3] one side line.
+// A custom 3x3 K_x (K_y = K_x^T) enters as, per line a, its outer weights
+// k0[a] = K_x[a][0], k2[a] = K_x[a][2] and the line's sum ks[a]: the kernels
+// evaluate K_x[a][0] s_- + K_x[a][1] s_0 + K_x[a][2] s_+ as
+// k2 (s_+ - s_0) - k0 (s_0 - s_-) + ks s_0, with the differences formed from
+// raw-value differences like the named kernels'.
 struct GradW {
     float wa;
     float r[4];
+    float k0[3], k2[3], ks[3];
 };
+
+// Gradient classes of the kernels: the centre line only (FD), three lines
+// w [-1 0 1] (Sobel, Scharr, Prewitt), any 3x3 (custom).
+enum { GK_3ROW = 0, GK_FD = 1, GK_CUSTOM = 2 };
 
 // Uniform batch: frame b = frame 0 shifted by b * stride.
 struct UniformArgs {
@@ -131,6 +141,7 @@ hipError_t occupancy_batch_disp(const Variant &v, int *blocks);
 // Kernel-side enum values (mirror include/sne.h).
 enum { KIND_F32 = 0, KIND_U16 = 1, KIND_F16 = 2, KIND_DISP = 3 };
 constexpr int kLenientFlag = 0x100;  // ORed into a kind: the lenient rule
+constexpr int kGradCustom = 4;       // SNE_GRAD_CUSTOM
 inline constexpr int base_kind(int kind) { return kind & ~kLenientFlag; }
 enum { AGG_MEAN = 0, AGG_MEDIAN = 1 };
 enum { OUT_F32 = 0, OUT_F16 = 1, OUT_RGBN = 2 };

@@ -504,6 +504,16 @@ template <typename V> __device__ __forceinline__ void store_stream(void *p, cons
     }
 }
 
+// s_b - s_a of two samples (a before b along the line): for depth
+// (z_a - z_b) s_a s_b, the form the named kernels use; for disparity d_b - d_a.
+template <int KIND>
+__device__ __forceinline__ float one_sided(float za, float zb, float sa, float sb) {
+    if constexpr (KIND == KIND_DISP)
+        return zb - za;
+    else
+        return (za - zb) * (sa * sb);
+}
+
 // One gradient line under the lenient rule: samples zm (minus side), z0
 // (middle), zp (plus side) with the filtered values sm, s0, sp and the line's
 // central difference `both` (sp - sm, formed as the strict path forms it).
@@ -546,12 +556,13 @@ __device__ __forceinline__ float lenient_combine(float c, bool hc, float a, bool
 // Output row r of a tile from the window (prev, cur, next); `pend` holds the
 // raw loads of row r + 1 on entry and those of row r + 1 + SNE_PREFETCH_ROWS
 // on exit.
-template <int KIND, bool FD, int AGG, int OUT, int PX, bool HALF, bool LEN>
+template <int KIND, int GK, int AGG, int OUT, int PX, bool HALF, bool LEN>
 __device__ __forceinline__ void tile_row(const FrameDesc &f, const InBuf &ib, const InBuf &rgbb,
                                          int r, int rend, int col, int col_off, int halo_off,
                                          const Edges &e, const GradW &gw, RawRow<KIND, PX> &pend,
                                          const RowState<PX> &prev, RowState<PX> &cur,
                                          RowState<PX> &next) {
+    constexpr bool FD = GK == GK_FD;
     finish_row<KIND, PX, HALF>(pend, next.row, e);
     load_raw<KIND, PX>(ib, r + 1 + SNE_PREFETCH_ROWS, col_off, halo_off, pend);  // prefetch
     // packed output: this row's RGBX bytes, in flight while the row is
@@ -591,6 +602,22 @@ __device__ __forceinline__ void tile_row(const FrameDesc &f, const InBuf &ib, co
         if constexpr (FD) {
             Gu = rc.D[k];
             Gv = V[c];
+        } else if constexpr (GK == GK_CUSTOM) {
+            // any 3x3 K_x: per line k2 (s_+ - s_0) - k0 (s_0 - s_-) + ks s_0;
+            // line a of K_y (column c + a - 1) is row a of K_x
+            Gu = 0.f;
+            Gv = 0.f;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const Row<PX> &X = a == 0 ? rp : (a == 1 ? rc : rn);
+                const float hp = one_sided<KIND>(X.z[c], X.z[c + 1], X.s[c], X.s[c + 1]);
+                const float hm = one_sided<KIND>(X.z[c - 1], X.z[c], X.s[c - 1], X.s[c]);
+                Gu += fmaf(gw.k2[a], hp, fmaf(-gw.k0[a], hm, gw.ks[a] * X.s[c]));
+                const int b = c + a - 1;
+                const float vp = one_sided<KIND>(rc.z[b], rn.z[b], rc.s[b], rn.s[b]);
+                const float vm = one_sided<KIND>(rp.z[b], rc.z[b], rp.s[b], rc.s[b]);
+                Gv += fmaf(gw.k2[a], vp, fmaf(-gw.k0[a], vm, gw.ks[a] * rc.s[b]));
+            }
         } else {
             // the 3-row filter divided by its centre weight (wa = side /
             // centre): n' scales as a whole, the normal does not change
@@ -598,7 +625,7 @@ __device__ __forceinline__ void tile_row(const FrameDesc &f, const InBuf &ib, co
             Gv = fmaf(gw.wa, V[c - 1] + V[c + 1], V[c]);
         }
         bool lenient_wave = false;
-        if constexpr (LEN) {
+        if constexpr (LEN && GK != GK_CUSTOM) {
             // a valid pixel without a full window somewhere in the wavefront
             if (__builtin_amdgcn_ballot_w64(!valid && zc > 0.f) != 0) {
                 lenient_wave = true;
@@ -715,7 +742,7 @@ __device__ __forceinline__ void tile_row(const FrameDesc &f, const InBuf &ib, co
 // strip (the frame, hence the buffer resource, stays wave-uniform).  Rows
 // past the frame read as 0 and are not stored.  The row loop is unrolled three
 // times with the window's roles rotating, so no register state is copied.
-template <int KIND, bool FD, int AGG, int OUT, int PX, bool HALF, bool LEN>
+template <int KIND, int GK, int AGG, int OUT, int PX, bool HALF, bool LEN>
 __device__ __forceinline__ void run_tile(const FrameDesc &f, int c0, int r0, int rows,
                                          const GradW &gw) {
     using T = typename Raw<KIND>::T;
@@ -746,7 +773,7 @@ __device__ __forceinline__ void run_tile(const FrameDesc &f, int c0, int r0, int
     make_pairs<PX>(A.row, B.row, A.below);
     load_raw<KIND, PX>(ib, rb + 1, col_off, halo_off, p0);
 #define SNE_ROW(I, P, X, Y, Z)                                                                  \
-    tile_row<KIND, FD, AGG, OUT, PX, HALF, LEN>(f, ib, rgbb, rb + (I), rend, col, col_off, halo_off, \
+    tile_row<KIND, GK, AGG, OUT, PX, HALF, LEN>(f, ib, rgbb, rb + (I), rend, col, col_off, halo_off, \
                                                 e, gw, P, X, Y, Z)
 #if SNE_PREFETCH_ROWS == 1
     for (int i = 0; i < n; i += 3) {
@@ -784,7 +811,7 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     return x * q + min(x, rem) + i;
 }
 
-template <int KIND, bool FD, int AGG, int OUT, int PX, bool HALF, bool LEN>
+template <int KIND, int GK, int AGG, int OUT, int PX, bool HALF, bool LEN>
 __global__ __launch_bounds__(kBlock) SNE_OCCUPANCY void sne_uniform_kernel(UniformArgs a) {
     const int b = a.xcd_remap ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     // wave-uniform by construction; readfirstlane lets the compiler keep the
@@ -806,7 +833,7 @@ __global__ __launch_bounds__(kBlock) SNE_OCCUPANCY void sne_uniform_kernel(Unifo
         if (f.rgb) f.rgb = static_cast<const char *>(a.f.rgb) + frame * a.rgb_fstride;
     // half-wave mode: a "band" is a pair of bands and a strip is 32 PX wide
     const int r0 = band * a.rows * (HALF ? 2 : 1);
-    run_tile<KIND, FD, AGG, OUT, PX, HALF, LEN>(f, strip * (HALF ? kWave / 2 : kWave) * PX, r0,
+    run_tile<KIND, GK, AGG, OUT, PX, HALF, LEN>(f, strip * (HALF ? kWave / 2 : kWave) * PX, r0,
                                                 a.rows, a.gw);
 }
 
@@ -852,7 +879,7 @@ __device__ __forceinline__ int find_frame(const int32_t *tile_start, int nframes
 // until all are drained.  The queues hold contiguous tile ranges, so
 // neighbouring tiles (which share halo rows) mostly run on one XCD and meet
 // in its L2, and the atomic increments are spread over eight addresses.
-template <int KIND, bool FD, int AGG, int OUT, int PX, bool HALF, bool LEN>
+template <int KIND, int GK, int AGG, int OUT, int PX, bool HALF, bool LEN>
 __global__ __launch_bounds__(kBlock) SNE_BATCH_OCCUPANCY void sne_batch_kernel(BatchArgs a) {
     const int lane = threadIdx.x & (kWave - 1);
     BatchHeader *head = static_cast<BatchHeader *>(a.table);
@@ -894,53 +921,53 @@ __global__ __launch_bounds__(kBlock) SNE_BATCH_OCCUPANCY void sne_batch_kernel(B
                 const int band = local / ns;
                 const int strip = local - band * ns;
                 const int r0 = band * a.rows * (HALF ? 2 : 1);
-                run_tile<KIND, FD, AGG, OUT, PX, HALF, LEN>(
+                run_tile<KIND, GK, AGG, OUT, PX, HALF, LEN>(
                     f, strip * (HALF ? kWave / 2 : kWave) * PX, r0, a.rows, a.gw);
             }
         }
     }
 }
 
-template <int KIND, bool FD, int AGG, int OUT, bool LEN>
+template <int KIND, int GK, int AGG, int OUT, bool LEN>
 hipError_t uniform_px(int px, const UniformArgs &a, int grid, hipStream_t s) {
     // px: columns per lane, + 100 for the half-wave mode
     switch (px) {
-    case 1: hipLaunchKernelGGL((sne_uniform_kernel<KIND, FD, AGG, OUT, 1, false, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((sne_uniform_kernel<KIND, FD, AGG, OUT, 2, false, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((sne_uniform_kernel<KIND, FD, AGG, OUT, 4, false, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 101: hipLaunchKernelGGL((sne_uniform_kernel<KIND, FD, AGG, OUT, 1, true, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 102: hipLaunchKernelGGL((sne_uniform_kernel<KIND, FD, AGG, OUT, 2, true, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 104: hipLaunchKernelGGL((sne_uniform_kernel<KIND, FD, AGG, OUT, 4, true, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((sne_uniform_kernel<KIND, GK, AGG, OUT, 1, false, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((sne_uniform_kernel<KIND, GK, AGG, OUT, 2, false, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((sne_uniform_kernel<KIND, GK, AGG, OUT, 4, false, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 101: hipLaunchKernelGGL((sne_uniform_kernel<KIND, GK, AGG, OUT, 1, true, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 102: hipLaunchKernelGGL((sne_uniform_kernel<KIND, GK, AGG, OUT, 2, true, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 104: hipLaunchKernelGGL((sne_uniform_kernel<KIND, GK, AGG, OUT, 4, true, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <int KIND, bool FD, int AGG, int OUT, bool LEN>
+template <int KIND, int GK, int AGG, int OUT, bool LEN>
 hipError_t batch_px(int px, const BatchArgs &a, int grid, hipStream_t s) {
     // px: columns per lane, + 100 for the half-wave mode
     switch (px) {
-    case 1: hipLaunchKernelGGL((sne_batch_kernel<KIND, FD, AGG, OUT, 1, false, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((sne_batch_kernel<KIND, FD, AGG, OUT, 2, false, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((sne_batch_kernel<KIND, FD, AGG, OUT, 4, false, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 101: hipLaunchKernelGGL((sne_batch_kernel<KIND, FD, AGG, OUT, 1, true, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 102: hipLaunchKernelGGL((sne_batch_kernel<KIND, FD, AGG, OUT, 2, true, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 104: hipLaunchKernelGGL((sne_batch_kernel<KIND, FD, AGG, OUT, 4, true, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((sne_batch_kernel<KIND, GK, AGG, OUT, 1, false, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((sne_batch_kernel<KIND, GK, AGG, OUT, 2, false, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((sne_batch_kernel<KIND, GK, AGG, OUT, 4, false, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 101: hipLaunchKernelGGL((sne_batch_kernel<KIND, GK, AGG, OUT, 1, true, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 102: hipLaunchKernelGGL((sne_batch_kernel<KIND, GK, AGG, OUT, 2, true, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 104: hipLaunchKernelGGL((sne_batch_kernel<KIND, GK, AGG, OUT, 4, true, LEN>), dim3(grid), dim3(kBlock), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <int KIND, bool FD, int AGG, int OUT, bool LEN>
+template <int KIND, int GK, int AGG, int OUT, bool LEN>
 hipError_t occupancy_px(int px, int *blocks) {
     const void *f = nullptr;
     switch (px) {
-    case 1: f = reinterpret_cast<const void *>(&sne_batch_kernel<KIND, FD, AGG, OUT, 1, false, LEN>); break;
-    case 2: f = reinterpret_cast<const void *>(&sne_batch_kernel<KIND, FD, AGG, OUT, 2, false, LEN>); break;
-    case 4: f = reinterpret_cast<const void *>(&sne_batch_kernel<KIND, FD, AGG, OUT, 4, false, LEN>); break;
-    case 101: f = reinterpret_cast<const void *>(&sne_batch_kernel<KIND, FD, AGG, OUT, 1, true, LEN>); break;
-    case 102: f = reinterpret_cast<const void *>(&sne_batch_kernel<KIND, FD, AGG, OUT, 2, true, LEN>); break;
-    case 104: f = reinterpret_cast<const void *>(&sne_batch_kernel<KIND, FD, AGG, OUT, 4, true, LEN>); break;
+    case 1: f = reinterpret_cast<const void *>(&sne_batch_kernel<KIND, GK, AGG, OUT, 1, false, LEN>); break;
+    case 2: f = reinterpret_cast<const void *>(&sne_batch_kernel<KIND, GK, AGG, OUT, 2, false, LEN>); break;
+    case 4: f = reinterpret_cast<const void *>(&sne_batch_kernel<KIND, GK, AGG, OUT, 4, false, LEN>); break;
+    case 101: f = reinterpret_cast<const void *>(&sne_batch_kernel<KIND, GK, AGG, OUT, 1, true, LEN>); break;
+    case 102: f = reinterpret_cast<const void *>(&sne_batch_kernel<KIND, GK, AGG, OUT, 2, true, LEN>); break;
+    case 104: f = reinterpret_cast<const void *>(&sne_batch_kernel<KIND, GK, AGG, OUT, 4, true, LEN>); break;
     default: return hipErrorInvalidValue;
     }
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, f, kBlock, 0);
@@ -949,28 +976,37 @@ hipError_t occupancy_px(int px, int *blocks) {
 // Dispatch on the runtime variant: filter class, aggregation, output type
 // and rule, then the tile's column class.  FN is uniform_px, batch_px or
 // occupancy_px; ARGS... are their arguments after px.
-#define SNE_DISPATCH_LEN(FN, KIND, FD, AGG, OUT, v, ...)                                   \
-    (((v).kind & kLenientFlag) ? FN<KIND, FD, AGG, OUT, true>((v).px, __VA_ARGS__)         \
-                              : FN<KIND, FD, AGG, OUT, false>((v).px, __VA_ARGS__))
-#define SNE_DISPATCH_OUT(FN, KIND, FD, AGG, v, ...)                                        \
-    ((v).out == OUT_F32 ? SNE_DISPATCH_LEN(FN, KIND, FD, AGG, OUT_F32, v, __VA_ARGS__)     \
-                        : SNE_DISPATCH_LEN(FN, KIND, FD, AGG, OUT_F16, v, __VA_ARGS__))
-#define SNE_DISPATCH_AGG(FN, KIND, FD, v, ...)                                             \
-    ((v).agg == AGG_MEAN ? SNE_DISPATCH_OUT(FN, KIND, FD, AGG_MEAN, v, __VA_ARGS__)        \
-                         : SNE_DISPATCH_OUT(FN, KIND, FD, AGG_MEDIAN, v, __VA_ARGS__))
+#define SNE_DISPATCH_LEN(FN, KIND, GK, AGG, OUT, v, ...)                                   \
+    (((v).kind & kLenientFlag) ? FN<KIND, GK, AGG, OUT, true>((v).px, __VA_ARGS__)         \
+                              : FN<KIND, GK, AGG, OUT, false>((v).px, __VA_ARGS__))
+#define SNE_DISPATCH_OUT(FN, KIND, GK, AGG, v, ...)                                        \
+    ((v).out == OUT_F32 ? SNE_DISPATCH_LEN(FN, KIND, GK, AGG, OUT_F32, v, __VA_ARGS__)     \
+                        : SNE_DISPATCH_LEN(FN, KIND, GK, AGG, OUT_F16, v, __VA_ARGS__))
+#define SNE_DISPATCH_AGG(FN, KIND, GK, v, ...)                                             \
+    ((v).agg == AGG_MEAN ? SNE_DISPATCH_OUT(FN, KIND, GK, AGG_MEAN, v, __VA_ARGS__)        \
+                         : SNE_DISPATCH_OUT(FN, KIND, GK, AGG_MEDIAN, v, __VA_ARGS__))
 #define SNE_DISPATCH(FN, KIND, v, ...)                                                     \
-    ((v).grad == 0 ? SNE_DISPATCH_AGG(FN, KIND, true, v, __VA_ARGS__)                      \
-                   : SNE_DISPATCH_AGG(FN, KIND, false, v, __VA_ARGS__))
+    ((v).grad == 0 ? SNE_DISPATCH_AGG(FN, KIND, GK_FD, v, __VA_ARGS__)                     \
+                   : SNE_DISPATCH_AGG(FN, KIND, GK_3ROW, v, __VA_ARGS__))
 
-#define SNE_DISPATCH_RGBN_AGG(FN, KIND, FD, v, ...)                                        \
-    ((v).agg == AGG_MEAN ? SNE_DISPATCH_LEN(FN, KIND, FD, AGG_MEAN, OUT_RGBN, v, __VA_ARGS__)  \
-                         : SNE_DISPATCH_LEN(FN, KIND, FD, AGG_MEDIAN, OUT_RGBN, v, __VA_ARGS__))
+#define SNE_DISPATCH_RGBN_AGG(FN, KIND, GK, v, ...)                                        \
+    ((v).agg == AGG_MEAN ? SNE_DISPATCH_LEN(FN, KIND, GK, AGG_MEAN, OUT_RGBN, v, __VA_ARGS__)  \
+                         : SNE_DISPATCH_LEN(FN, KIND, GK, AGG_MEDIAN, OUT_RGBN, v, __VA_ARGS__))
 
 template <int KIND>
 hipError_t uniform_variant(const Variant &v, const UniformArgs &a, int grid, hipStream_t s) {
     if (v.out == OUT_RGBN)  // the packed output exists for single frames and uniform batches
-        return (v.grad == 0 ? SNE_DISPATCH_RGBN_AGG(uniform_px, KIND, true, v, a, grid, s)
-                            : SNE_DISPATCH_RGBN_AGG(uniform_px, KIND, false, v, a, grid, s));
+        return (v.grad == 0 ? SNE_DISPATCH_RGBN_AGG(uniform_px, KIND, GK_FD, v, a, grid, s)
+                            : SNE_DISPATCH_RGBN_AGG(uniform_px, KIND, GK_3ROW, v, a, grid, s));
+    if (v.grad == kGradCustom) {  // custom kernels: single frames and uniform batches, strict
+        if (v.agg == AGG_MEAN)
+            return v.out == OUT_F32
+                       ? uniform_px<KIND, GK_CUSTOM, AGG_MEAN, OUT_F32, false>(v.px, a, grid, s)
+                       : uniform_px<KIND, GK_CUSTOM, AGG_MEAN, OUT_F16, false>(v.px, a, grid, s);
+        return v.out == OUT_F32
+                   ? uniform_px<KIND, GK_CUSTOM, AGG_MEDIAN, OUT_F32, false>(v.px, a, grid, s)
+                   : uniform_px<KIND, GK_CUSTOM, AGG_MEDIAN, OUT_F16, false>(v.px, a, grid, s);
+    }
     return SNE_DISPATCH(uniform_px, KIND, v, a, grid, s);
 }
 template <int KIND>

@@ -334,6 +334,7 @@ extern "C" {
 int sne_server_create(sne_server **out, sne_ctx *ctx, const sne_server_config *cfg) {
     if (!out) return SNE_ERR_ARG;
     *out = nullptr;
+    if (cfg && cfg->grad == SNE_GRAD_CUSTOM) return SNE_ERR_UNSUPPORTED;
     if (!ctx || !cfg || !valid_config(*cfg)) return SNE_ERR_ARG;
     if (hipSetDevice(ctx->device) != hipSuccess) return SNE_ERR_HIP;
     sne_server *s = new sne_server();

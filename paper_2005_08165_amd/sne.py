@@ -32,7 +32,7 @@ STATUS = {0: "SNE_OK", -1: "SNE_ERR_ARG", -2: "SNE_ERR_UNSUPPORTED", -3: "SNE_ER
 
 KIND = {"depth_f32": 0, "depth_u16": 1, "depth_f16": 2, "disparity_f32": 3}
 KIND_DTYPE = {0: torch.float32, 1: torch.uint16, 2: torch.float16, 3: torch.float32}
-GRAD = {"fd": 0, "sobel": 1, "scharr": 2, "prewitt": 3}
+GRAD = {"fd": 0, "sobel": 1, "scharr": 2, "prewitt": 3, "custom": 4}
 AGG = {"mean": 0, "median": 1}
 OUT = {"f32": 0, "f16": 1}
 OUT_DTYPE = {0: torch.float32, 1: torch.float16}
@@ -135,6 +135,7 @@ _SIGS = {
                            _int, _int, _int, _vp, _i64, _i64, _vp, _i64, _i64, _vp, _i64, _i64,
                            _vp], _int),
     "sne_set_intrinsics_table": ([_vp, ctypes.POINTER(Intrinsics), _i32], _int),
+    "sne_set_gradient_kernel": ([_vp, ctypes.POINTER(ctypes.c_float)], _int),
     "sne_estimate_batched": ([_vp, ctypes.POINTER(FrameDesc), _i32, _int, _int, _int, _int, _vp],
                              _int),
     "sne_estimate_batched_noalloc": ([_vp, ctypes.POINTER(FrameDesc), _i32, _int, _int, _int,
@@ -359,6 +360,15 @@ class Context:
     def set_intrinsics_table(self, Ks: Sequence[Sequence[float]]):
         arr = (Intrinsics * len(Ks))(*[_K(k) for k in Ks])
         check("sne_set_intrinsics_table", lib().sne_set_intrinsics_table(self._h, arr, len(Ks)))
+
+    def set_gradient_kernel(self, kx) -> None:
+        """sne_set_gradient_kernel: the 3x3 K_x (row-major) that grad="custom"
+        uses on this context (K_y = K_x^T)."""
+        vals = [float(x) for row in kx for x in row]
+        if len(vals) != 9:
+            raise ValueError("a 3x3 kernel is expected")
+        arr = (ctypes.c_float * 9)(*vals)
+        check("sne_set_gradient_kernel", lib().sne_set_gradient_kernel(self._h, arr))
 
     # -- compute -------------------------------------------------------------
     def estimate(self, raw: torch.Tensor, K, kind="depth_f32", grad="fd", agg="mean", out="f32",
