@@ -2,6 +2,7 @@
 #include "sne_sched.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 
 namespace sne {
@@ -227,6 +228,69 @@ bool Scheduler::output_offset(uint64_t ticket, uint64_t *off) const {
     if (it == live_.end()) return false;
     *off = it->second->out_offset;
     return true;
+}
+
+Service::Service(const Config &cfg, Executor *ex, std::function<double()> clock,
+                 std::function<void()> on_start)
+    : sched_(cfg, ex), clock_(std::move(clock)) {
+    worker_ = std::thread(&Service::loop, this, std::move(on_start));
+}
+
+Service::~Service() { stop(); }
+
+void Service::stop() {
+    stop_.store(true, std::memory_order_relaxed);
+    if (worker_.joinable()) worker_.join();
+}
+
+void Service::loop(std::function<void()> on_start) {
+    if (on_start) on_start();
+    while (!stop_.load(std::memory_order_relaxed)) {
+        bool busy;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            sched_.step(clock_());
+            busy = !sched_.idle();
+        }
+        if (busy)
+            std::this_thread::yield();
+        else
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+}
+
+int Service::submit(Request r, uint64_t *ticket) {
+    std::lock_guard<std::mutex> lk(mu_);
+    if (r.t_arrival < 0) r.t_arrival = clock_();
+    return sched_.submit(r, ticket);
+}
+
+std::vector<Request> Service::take_completed(size_t max) {
+    std::lock_guard<std::mutex> lk(mu_);
+    return sched_.take_completed(max);
+}
+
+int Service::release(uint64_t ticket) {
+    std::lock_guard<std::mutex> lk(mu_);
+    return sched_.release(ticket);
+}
+
+bool Service::drain(double timeout_s) {
+    const auto t_end =
+        std::chrono::steady_clock::now() + std::chrono::duration<double>(timeout_s);
+    for (;;) {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            if (sched_.idle()) return true;
+        }
+        if (std::chrono::steady_clock::now() > t_end) return false;
+        std::this_thread::sleep_for(std::chrono::microseconds(50));
+    }
+}
+
+void Service::reset_stats() {
+    std::lock_guard<std::mutex> lk(mu_);
+    sched_.reset_stats();
 }
 
 double quantile(std::vector<double> v, double q) {

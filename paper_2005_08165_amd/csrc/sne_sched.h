@@ -18,9 +18,12 @@
 
 #include <stdint.h>
 
+#include <atomic>
 #include <deque>
 #include <functional>
 #include <map>
+#include <mutex>
+#include <thread>
 #include <vector>
 
 namespace sne {
@@ -150,6 +153,45 @@ private:
     std::deque<Request *> completed_;
     std::map<uint64_t, Request *> live_;  // ticket -> request (until release)
     Stats stats_;
+};
+
+// The scheduler as a service for many threads: one worker thread runs
+// step() whenever it is not idle (and polls every 20 us when it is); any
+// thread may submit, take completions, release outputs, read statistics or
+// wait for the queue to drain.  Every access to the scheduler, and every call
+// of the executor (from step()), happens under one mutex.  `clock` returns
+// seconds on the service's clock; `on_start` runs first on the worker
+// thread (the server binds its GPU there).
+class Service {
+public:
+    Service(const Config &cfg, Executor *ex, std::function<double()> clock,
+            std::function<void()> on_start = {});
+    ~Service();  // stops the worker; drain first to finish queued work
+
+    // t_arrival < 0: now.  Returns 0, -3 (larger than the budget) or -6 (full).
+    int submit(Request r, uint64_t *ticket);
+    std::vector<Request> take_completed(size_t max);
+    // 0, -5 (still queued or running) or -1 (unknown ticket).
+    int release(uint64_t ticket);
+    // Waits until nothing is queued or running; false on timeout.
+    bool drain(double timeout_s);
+    // f(const Scheduler &) under the lock.
+    template <typename F> auto inspect(F f) {
+        std::lock_guard<std::mutex> lk(mu_);
+        return f(static_cast<const Scheduler &>(sched_));
+    }
+    void reset_stats();
+    double now() const { return clock_(); }
+    void stop();
+
+private:
+    void loop(std::function<void()> on_start);
+
+    Scheduler sched_;
+    std::function<double()> clock_;
+    std::mutex mu_;
+    std::atomic<bool> stop_{false};
+    std::thread worker_;
 };
 
 // Quantile of a sample (nearest rank, q in [0, 1]); 0 if empty.

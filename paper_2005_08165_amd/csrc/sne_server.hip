@@ -259,10 +259,8 @@ struct sne_server {
     sne_server_config cfg{};
     uint8_t *arena = nullptr;
     sne::HipExecutor ex;
-    sne::sched::Scheduler *sched = nullptr;
-    std::mutex mu;
-    std::thread worker;
-    std::atomic<bool> stop{false};
+    // the scheduler, its lock and its worker thread
+    sne::sched::Service *svc = nullptr;
     sne::Clock::time_point t0;
 
     double now() const {
@@ -272,24 +270,6 @@ struct sne_server {
 
 namespace sne {
 namespace {
-
-void worker_loop(sne_server *srv) {
-    // the device was usable when the server was created; a failure here
-    // surfaces as failed batches
-    (void)hipSetDevice(srv->ctx->device);
-    while (!srv->stop.load(std::memory_order_relaxed)) {
-        bool busy;
-        {
-            std::lock_guard<std::mutex> lk(srv->mu);
-            srv->sched->step(srv->now());
-            busy = !srv->sched->idle();
-        }
-        if (busy)
-            std::this_thread::yield();
-        else
-            std::this_thread::sleep_for(std::chrono::microseconds(20));
-    }
-}
 
 bool valid_config(const sne_server_config &c) {
     return valid_enum(c.kind, c.grad, c.agg, c.out_type) && c.max_inflight >= 1 &&
@@ -360,10 +340,13 @@ int sne_server_create(sne_server **out, sne_ctx *ctx, const sne_server_config *c
     sc.budget_bytes = (uint64_t)cfg->hbm_budget_bytes;
     sc.align = 256;
     sc.queue_capacity = (size_t)cfg->queue_capacity;
-    s->sched = new sched::Scheduler(sc, &s->ex);
     s->t0 = Clock::now();
     ctx->n_servers.fetch_add(1);
-    s->worker = std::thread(worker_loop, s);
+    // the device was usable when the server was created; a failure on the
+    // worker thread surfaces as failed batches
+    const int device = ctx->device;
+    s->svc = new sched::Service(
+        sc, &s->ex, [s] { return s->now(); }, [device] { (void)hipSetDevice(device); });
     *out = s;
     return SNE_OK;
 }
@@ -387,20 +370,15 @@ int sne_server_submit(sne_server *srv, const sne_request *req, uint64_t *ticket)
     r.in = req->in;
     r.in_pitch = req->in_pitch;
     r.ready = req->ready;
-    std::lock_guard<std::mutex> lk(srv->mu);
-    r.t_arrival = req->t_arrival >= 0 ? req->t_arrival : srv->now();
-    const int rc = srv->sched->submit(r, ticket);
+    r.t_arrival = req->t_arrival >= 0 ? req->t_arrival : -1.0;  // < 0: now
+    const int rc = srv->svc->submit(r, ticket);
     if (rc != 0) return rc == -3 ? SNE_ERR_BUDGET : SNE_ERR_FULL;
     return SNE_OK;
 }
 
 int sne_server_poll(sne_server *srv, sne_completion *out, int32_t max, int32_t *n) {
     if (!srv || !n || max < 0 || (max > 0 && !out)) return SNE_ERR_ARG;
-    std::vector<sched::Request> done;
-    {
-        std::lock_guard<std::mutex> lk(srv->mu);
-        done = srv->sched->take_completed((size_t)max);
-    }
+    const std::vector<sched::Request> done = srv->svc->take_completed((size_t)max);
     const size_t oe = out_elem(srv->cfg.out_type);
     for (size_t i = 0; i < done.size(); ++i) {
         const sched::Request &q = done[i];
@@ -422,45 +400,35 @@ int sne_server_poll(sne_server *srv, sne_completion *out, int32_t max, int32_t *
 
 int sne_server_release(sne_server *srv, uint64_t ticket) {
     if (!srv) return SNE_ERR_ARG;
-    std::lock_guard<std::mutex> lk(srv->mu);
-    const int rc = srv->sched->release(ticket);
+    const int rc = srv->svc->release(ticket);
     return rc == 0 ? SNE_OK : (rc == -5 ? SNE_ERR_STATE : SNE_ERR_ARG);
 }
 
 int sne_server_drain(sne_server *srv, double timeout_s) {
     if (!srv) return SNE_ERR_ARG;
-    const double t_end = srv->now() + timeout_s;
-    for (;;) {
-        {
-            std::lock_guard<std::mutex> lk(srv->mu);
-            if (srv->sched->idle()) return SNE_OK;
-        }
-        if (srv->now() > t_end) return SNE_ERR_STATE;
-        std::this_thread::sleep_for(std::chrono::microseconds(50));
-    }
+    return srv->svc->drain(timeout_s) ? SNE_OK : SNE_ERR_STATE;
 }
 
 int sne_server_get_stats(sne_server *srv, sne_server_stats *st) {
     if (!srv || !st) return SNE_ERR_ARG;
-    std::lock_guard<std::mutex> lk(srv->mu);
-    fill_stats(srv->sched->stats(), srv->sched->arena_free(), st);
+    srv->svc->inspect([st](const sched::Scheduler &sc) {
+        fill_stats(sc.stats(), sc.arena_free(), st);
+        return 0;
+    });
     return SNE_OK;
 }
 
 int sne_server_reset_stats(sne_server *srv) {
     if (!srv) return SNE_ERR_ARG;
-    std::lock_guard<std::mutex> lk(srv->mu);
-    srv->sched->reset_stats();
+    srv->svc->reset_stats();
     return SNE_OK;
 }
 
 int sne_server_destroy(sne_server *srv) {
     if (!srv) return SNE_OK;
     (void)sne_server_drain(srv, 30.0);
-    srv->stop = true;
-    if (srv->worker.joinable()) srv->worker.join();
+    delete srv->svc;  // stops the worker thread
     srv->ex.destroy();
-    delete srv->sched;
     if (srv->arena) (void)hipFree(srv->arena);
     srv->ctx->n_servers.fetch_sub(1);
     delete srv;

@@ -34,6 +34,31 @@ def test_scheduler_cases_sanitized(tmp_path):
     _build_and_run(tmp_path, ["-fsanitize=address,undefined", "-fno-omit-frame-pointer"])
 
 
+THREADS_SRC = [os.path.join(HERE, "sched_threads.cpp"),
+               os.path.join(ROOT, "paper_2005_08165_amd", "csrc", "sne_sched.cpp")]
+
+
+def _build_and_run_threads(tmp_path, extra):
+    exe = str(tmp_path / "sched_threads")
+    subprocess.check_call(["g++", "-std=c++17", "-O1", "-g", "-Wall", "-pthread"] + extra +
+                          THREADS_SRC + ["-o", exe])
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "ALL OK" in r.stdout
+    assert "WARNING: ThreadSanitizer" not in r.stderr, r.stderr
+
+
+@pytest.mark.parametrize("sanitizer", ["none", "thread", "address,undefined"])
+def test_scheduler_service_many_threads(tmp_path, sanitizer):
+    """The locking and worker thread of the serving loop (sched::Service),
+    driven by 8 producer threads, 2 clients and a statistics reader against
+    a fake executor with wall-clock batch times; under ThreadSanitizer too."""
+    if shutil.which("g++") is None:
+        pytest.skip("no g++")
+    extra = [] if sanitizer == "none" else ["-fsanitize=" + sanitizer, "-fno-omit-frame-pointer"]
+    _build_and_run_threads(tmp_path, extra)
+
+
 def test_capacity_simulator_20k_fps():
     """The exported capacity model (host only): 64 streams, 20k frames/s of
     the serving resolutions against a GPU model; every frame completes, the
