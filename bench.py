@@ -147,6 +147,8 @@ def disparity_batch(torch, S, sne, reps=300, warmup=30):
             "tile": {"cols_per_lane": tile[0], "rows": tile[1], "lanes": tile[2]},
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
                          "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                         "traffic": measured_traffic(
+                             "batch128_375x1242_f32disparity_scharr_median", tile),
                          "algorithmic_bytes_per_launch": px * 17}}
 
 
