@@ -82,14 +82,18 @@ def _prep(raw: np.ndarray, kind: str) -> np.ndarray:
     return raw
 
 
+CUSTOM_SIZES = {3: 4, 5: 5, 7: 6}
+
+
 def _grad(grad):
-    """(code, kx) of a gradient filter: a name, or a 3x3 K_x (custom)."""
+    """(code, kx) of a gradient filter: a name, or a 3x3, 5x5 or 7x7 K_x
+    (custom)."""
     if isinstance(grad, str):
         return GRADS[grad], None
     kx = np.ascontiguousarray(np.asarray(grad, dtype=np.float64))
-    if kx.shape != (3, 3):
-        raise ValueError("a custom gradient kernel is 3x3")
-    return 4, kx
+    if kx.ndim != 2 or kx.shape[0] != kx.shape[1] or kx.shape[0] not in CUSTOM_SIZES:
+        raise ValueError("a custom gradient kernel is 3x3, 5x5 or 7x7")
+    return CUSTOM_SIZES[kx.shape[0]], kx
 
 
 def estimate(raw: np.ndarray, kind: str, K: Sequence[float], grad="fd",
@@ -97,10 +101,11 @@ def estimate(raw: np.ndarray, kind: str, K: Sequence[float], grad="fd",
              mcount: bool = False, rule: str = "strict"):
     """Normals [3,H,W] float64 and mask [H,W] uint8 of one image.
 
-    ``rule``: "strict" (a fully valid 3x3 window at an interior pixel) or
+    ``rule``: "strict" (a fully valid filter window at an interior pixel) or
     "lenient" (valid neighbours only, one-sided gradient lines; see the header
-    of sne_oracle.c).  ``grad``: "fd", "sobel", "scharr", "prewitt" or a 3x3
-    custom K_x (row-major, K_y = K_x^T).
+    of sne_oracle.c).  ``grad``: "fd", "sobel", "scharr", "prewitt" or a 3x3,
+    5x5 or 7x7 custom K_x (row-major, K_y = K_x^T; Q_i stays the
+    8-neighbourhood).
 
     K = (fx, fy, u0, v0) as the values the caller wants used (pass the FP32
     values a GPU run used to compare like with like).  With ``unnorm`` the

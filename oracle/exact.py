@@ -33,41 +33,45 @@ def pixel(img, v, u, K, grad="fd", agg="mean", disparity=False, tc=1, rule="stri
     """Return (mask, nprime or None, normal tuple of floats) for pixel (v, u).
 
     img: list of rows of ints (0 = invalid); K = (fx, fy, u0, v0) rationals;
-    grad: a kernel name or a 3x3 K_x of rationals (custom, K_y = K_x^T).
+    grad: a kernel name or a square K_x of odd size n = 2R+1 (custom, rows
+    v-R..v+R, K_y = K_x^T); the neighbourhood Q_i is the 8 neighbours
+    whatever the filter size, and every sample the filter reads must be valid.
     rule "lenient": the reading for holes and borders stated in the header of
     sne_oracle.c, restated by pixel_lenient below."""
     if rule == "lenient":
         return pixel_lenient(img, v, u, K, grad, agg, disparity, tc)
     H, W = len(img), len(img[0])
     fx, fy, u0, v0 = (Fr(x) for x in K)
-    if not (1 <= u <= W - 2 and 1 <= v <= H - 2):
+    k = KX[grad] if isinstance(grad, str) else [[Fr(x) for x in row] for row in grad]
+    R = len(k) // 2
+    if not (R <= u <= W - 1 - R and R <= v <= H - 1 - R):
         return 0, None, (0.0, 0.0, 0.0)
-    win = [[img[v + a][u + b] for b in (-1, 0, 1)] for a in (-1, 0, 1)]
+    # win[a][b]: sample at offset (a - R, b - R)
+    win = [[img[v + a][u + b] for b in range(-R, R + 1)] for a in range(-R, R + 1)]
     if any(x <= 0 for row in win for x in row):
         return 0, None, (0.0, 0.0, 0.0)
-    c0 = win[1][1]
-    if all(x == c0 for row in win for x in row):
+    c0 = win[R][R]
+    nbr = [(a, b) for a in (R - 1, R, R + 1) for b in (R - 1, R, R + 1) if (a, b) != (R, R)]
+    if all(win[a][b] == c0 for a, b in nbr):
         return 1, None, (0.0, 0.0, -1.0)
     # depth and the filtered image
     z = [[(fx * Fr(tc) / Fr(x)) if disparity else Fr(x) for x in row] for row in win]
-    s = [[Fr(win[a][b]) if disparity else 1 / z[a][b] for b in range(3)] for a in range(3)]
-    k = KX[grad] if isinstance(grad, str) else [[Fr(x) for x in row] for row in grad]
-    Gu = sum(k[a][b] * s[a][b] for a in range(3) for b in range(3))
-    Gv = sum(k[b][a] * s[a][b] for a in range(3) for b in range(3))
+    n = 2 * R + 1
+    s = [[Fr(win[a][b]) if disparity else 1 / z[a][b] for b in range(n)] for a in range(n)]
+    Gu = sum(k[a][b] * s[a][b] for a in range(n) for b in range(n))
+    Gv = sum(k[b][a] * s[a][b] for a in range(n) for b in range(n))
     nx = Gu if disparity else fx * Gu
     ny = Gv if disparity else fy * Gv
 
     def P(a, b):
-        return (z[a][b] * (Fr(u + b - 1) - u0) / fx,
-                z[a][b] * (Fr(v + a - 1) - v0) / fy,
+        return (z[a][b] * (Fr(u + b - R) - u0) / fx,
+                z[a][b] * (Fr(v + a - R) - v0) / fy,
                 z[a][b])
 
-    p = P(1, 1)
+    p = P(R, R)
     cands = []
-    for a in range(3):
-        for b in range(3):
-            if (a, b) == (1, 1) or win[a][b] == c0:
-                continue
+    for a, b in nbr:
+        if win[a][b] != c0:
             q = P(a, b)
             dX, dY, dZ = q[0] - p[0], q[1] - p[1], q[2] - p[2]
             cands.append((dX * nx + dY * ny) / dZ)

@@ -80,6 +80,15 @@
  * columns u-1..u+1; step 5 then sums K_x[a][b] s(v+a-1, u+b-1) row by row
  * (and K_y column by column) exactly as for the built-in kernels.  The
  * lenient rule is defined for the built-in kernels only.
+ *
+ * Larger custom kernels (grad = 5: 5x5, grad = 6: 7x7).  Fig. 2 compares
+ * gradient filters of several sizes.  A (2R+1)x(2R+1) K_x (R = 2, 3) is
+ * passed as kx[(2R+1)^2], row-major, rows v-R..v+R; K_y = K_x^T again and
+ * step 5 sums over the whole (2R+1)x(2R+1) window.  Only the gradient
+ * filters grow: Q_i stays the 8-connected neighbourhood (steps 2, 7, 8), as
+ * the method estimates normals from an 8-connected neighbourhood (Sec. IV-B).
+ * Step 1 then reads: the mask is 1 iff R <= u <= W-1-R, R <= v <= H-1-R and
+ * every sample of the (2R+1)x(2R+1) window is valid.
  */
 #include <math.h>
 #include <stddef.h>
@@ -95,7 +104,8 @@
 
 enum { K_DEPTH_F32 = 0, K_DEPTH_U16 = 1, K_DEPTH_F16 = 2, K_DISP_F32 = 3,
        K_DEPTH_F64 = 4, K_DISP_F64 = 5 };
-enum { G_FD = 0, G_SOBEL = 1, G_SCHARR = 2, G_PREWITT = 3, G_CUSTOM = 4 };
+enum { G_FD = 0, G_SOBEL = 1, G_SCHARR = 2, G_PREWITT = 3, G_CUSTOM = 4, G_CUSTOM5 = 5,
+       G_CUSTOM7 = 6 };
 enum { A_MEAN = 0, A_MEDIAN = 1 };
 
 /* Horizontal-derivative kernels K_x[row][col]; row/col index = offset + 1. */
@@ -112,12 +122,22 @@ typedef struct {
     int64_t pitch;               /* elements between rows */
     double fx, fy, u0, v0, tc;
     int grad, agg, rule;
-    const double *kx;            /* grad = G_CUSTOM: K_x row-major */
+    const double *kx;            /* grad >= G_CUSTOM: K_x row-major */
 } orc_img;
 
-/* The horizontal-derivative kernel of the image's gradient filter. */
+/* The horizontal-derivative kernel of a built-in or 3x3 custom filter. */
 static const double (*kernel_of(const orc_img *im))[3] {
     return im->grad == G_CUSTOM ? (const double (*)[3])im->kx : KX[im->grad];
+}
+
+/* Half-width R of the gradient filter's (2R+1)x(2R+1) window. */
+static int radius_of(int grad) { return grad == G_CUSTOM5 ? 2 : grad == G_CUSTOM7 ? 3 : 1; }
+
+/* K_x[a][b] of the image's gradient filter, 0 <= a, b <= 2R. */
+static double kx_at(const orc_img *im, int a, int b) {
+    const int R = radius_of(im->grad);
+    if (R == 1) return kernel_of(im)[a][b];
+    return im->kx[a * (2 * R + 1) + b];
 }
 
 /* IEEE binary16 -> double, from the format's definition. */
@@ -160,20 +180,23 @@ static void pixel(const orc_img *im, int v, int u, double out[3], unsigned char 
     if (unnorm) unnorm[0] = unnorm[1] = unnorm[2] = 0.0;
     *mask = 0;
     *m_out = -1;
-    if (u < 1 || u > im->W - 2 || v < 1 || v > im->H - 2) return;
+    /* the gradient filters' window: (2R+1)x(2R+1) samples around p; the
+     * 8-neighbourhood Q_i is its centre 3x3 block (offsets R-1..R+1) */
+    const int R = radius_of(im->grad), N = 2 * R + 1;
+    if (u < R || u > im->W - 1 - R || v < R || v > im->H - 1 - R) return;
 
-    double raw[3][3];
-    for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) {
-            raw[a][b] = raw_at(im, v + a - 1, u + b - 1);
+    double raw[7][7];
+    for (int a = 0; a < N; ++a)
+        for (int b = 0; b < N; ++b) {
+            raw[a][b] = raw_at(im, v + a - R, u + b - R);
             if (!(isfinite(raw[a][b]) && raw[a][b] > 0.0)) return;
         }
     *mask = 1;
 
     int all_equal = 1;
-    for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b)
-            if (raw[a][b] != raw[1][1]) all_equal = 0;
+    for (int a = R - 1; a <= R + 1; ++a)
+        for (int b = R - 1; b <= R + 1; ++b)
+            if (raw[a][b] != raw[R][R]) all_equal = 0;
     if (all_equal) {
         out[2] = -1.0;
         *m_out = 0;
@@ -181,37 +204,37 @@ static void pixel(const orc_img *im, int v, int u, double out[3], unsigned char 
     }
 
     const int disp = is_disparity(im->kind);
-    double z[3][3], s[3][3];
-    for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) {
+    double z[7][7], s[7][7];
+    for (int a = 0; a < N; ++a)
+        for (int b = 0; b < N; ++b) {
             z[a][b] = disp ? im->fx * im->tc / raw[a][b] : raw[a][b];
             s[a][b] = disp ? raw[a][b] : 1.0 / z[a][b];
         }
 
     /* Filters 1 and 2: correlation with K_x and K_y = K_x^T, line by line. */
-    const double (*K)[3] = kernel_of(im);
     double Gu = 0.0, Gv = 0.0;
-    for (int a = 0; a < 3; ++a) {          /* rows of K_x */
+    for (int a = 0; a < N; ++a) {          /* rows of K_x */
         double line = 0.0;
-        for (int b = 0; b < 3; ++b) line += K[a][b] * s[a][b];
+        for (int b = 0; b < N; ++b) line += kx_at(im, a, b) * s[a][b];
         Gu += line;
     }
-    for (int b = 0; b < 3; ++b) {          /* columns of K_y: K_y[a][b] = K_x[b][a] */
+    for (int b = 0; b < N; ++b) {          /* columns of K_y: K_y[a][b] = K_x[b][a] */
         double line = 0.0;
-        for (int a = 0; a < 3; ++a) line += K[b][a] * s[a][b];
+        for (int a = 0; a < N; ++a) line += kx_at(im, b, a) * s[a][b];
         Gv += line;
     }
     const double nx = disp ? Gu : im->fx * Gu;
     const double ny = disp ? Gv : im->fy * Gv;
 
-    /* Back-projected window points. */
+    /* Back-projected points of p and its 8 neighbours. */
     double P[3][3][3];
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) {
             const double uq = (double)(u + b - 1), vq = (double)(v + a - 1);
-            P[a][b][0] = z[a][b] * (uq - im->u0) / im->fx;
-            P[a][b][1] = z[a][b] * (vq - im->v0) / im->fy;
-            P[a][b][2] = z[a][b];
+            const double zq = z[R - 1 + a][R - 1 + b];
+            P[a][b][0] = zq * (uq - im->u0) / im->fx;
+            P[a][b][1] = zq * (vq - im->v0) / im->fy;
+            P[a][b][2] = zq;
         }
 
     double c[8];
@@ -219,7 +242,7 @@ static void pixel(const orc_img *im, int v, int u, double out[3], unsigned char 
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) {
             if (a == 1 && b == 1) continue;
-            if (raw[a][b] == raw[1][1]) continue;     /* dZ = 0: left out */
+            if (raw[R - 1 + a][R - 1 + b] == raw[R][R]) continue;  /* dZ = 0: left out */
             const double dX = P[a][b][0] - P[1][1][0];
             const double dY = P[a][b][1] - P[1][1][1];
             const double dZ = P[a][b][2] - P[1][1][2];
@@ -399,9 +422,9 @@ static int check_args(const void *raw, int kind, int H, int W, int64_t pitch, do
                       double fy, int grad, int agg, int rule, const double *kx) {
     if (!raw || H < 1 || W < 1 || pitch < W) return ORC_EARG;
     if (kind < K_DEPTH_F32 || kind > K_DISP_F64) return ORC_EARG;
-    if (grad < G_FD || grad > G_CUSTOM || agg < A_MEAN || agg > A_MEDIAN) return ORC_EARG;
+    if (grad < G_FD || grad > G_CUSTOM7 || agg < A_MEAN || agg > A_MEDIAN) return ORC_EARG;
     if (rule != 0 && rule != 1) return ORC_EARG;
-    if ((grad == G_CUSTOM) != (kx != NULL) || (grad == G_CUSTOM && rule == 1)) return ORC_EARG;
+    if ((grad >= G_CUSTOM) != (kx != NULL) || (grad >= G_CUSTOM && rule == 1)) return ORC_EARG;
     if (!(fx > 0.0) || !(fy > 0.0)) return ORC_EARG;
     if (is_disparity(kind) && fx != fy) return ORC_EARG;
     return ORC_OK;

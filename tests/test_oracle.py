@@ -668,5 +668,101 @@ def test_custom_kernel_argument_rules():
     raw = np.full((5, 5), 2.0, np.float32)
     with pytest.raises(ValueError):
         oracle.estimate(raw, "depth_f32", (5, 5, 2, 2), np.ones((2, 3)), "mean")
-    with pytest.raises(ValueError):  # the lenient rule is defined for the named kernels only
-        oracle.estimate(raw, "depth_f32", (5, 5, 2, 2), np.ones((3, 3)), "mean", rule="lenient")
+    for n in (2, 4, 9):
+        with pytest.raises(ValueError):
+            oracle.estimate(raw, "depth_f32", (5, 5, 2, 2), np.ones((n, n)), "mean")
+    for n in (3, 5, 7):
+        with pytest.raises(ValueError):  # the lenient rule: the named kernels only
+            oracle.estimate(raw, "depth_f32", (5, 5, 2, 2), np.ones((n, n)), "mean",
+                            rule="lenient")
+
+
+# --------------------------------------------------------------------------
+# 5x5 and 7x7 custom gradient kernels (filter sizes, Fig. 2)
+# --------------------------------------------------------------------------
+
+def _embed(kx3, n):
+    """A 3x3 kernel in the centre of an n x n kernel of zeros."""
+    k = np.zeros((n, n))
+    c = n // 2
+    k[c - 1:c + 2, c - 1:c + 2] = kx3
+    return k
+
+
+def _window_mask(raw, R):
+    """Brute force of the strict mask for a (2R+1)^2 filter window: inside
+    the frame and every sample finite and > 0."""
+    H, W = raw.shape
+    ok = np.isfinite(raw) & (raw > 0)
+    m = np.zeros((H, W), np.uint8)
+    for v in range(R, H - R):
+        for u in range(R, W - R):
+            m[v, u] = ok[v - R:v + R + 1, u - R:u + R + 1].all()
+    return m
+
+
+@pytest.mark.parametrize("n", [5, 7])
+@pytest.mark.parametrize("agg", AGGS)
+def test_large_kernel_with_zero_ring_is_the_3x3_one(n, agg):
+    """A named 3x3 kernel padded with zeros to 5x5 or 7x7 gives, wherever
+    the larger window is valid, the 3x3 normals bit for bit in FP64 (added
+    zero taps and zero lines change no sum); the mask is the brute-force
+    (2R+1)^2 window test, so it shrinks at borders and around holes."""
+    fr = S.make_cluttered(93, S.Camera(48, 64, 48.1, 48.1, 31.5, 23.5))
+    raw, K = fr.raw.numpy(), fr.cam.as_tuple()
+    for name in ("sobel", "fd", "scharr"):
+        n3, m3 = oracle.estimate(raw, "depth_f32", K, name, agg)
+        nn, mn = oracle.estimate(raw, "depth_f32", K, _embed(BUILTIN_KX[name], n), agg)
+        assert (mn == _window_mask(raw, n // 2)).all(), name
+        assert mn.sum() > 0.15 * raw.size and not (mn & ~m3).any()
+        keep = mn.astype(bool)
+        assert np.array_equal(nn[:, keep], n3[:, keep]), name
+        assert (nn[:, ~keep] == 0).all()
+
+
+@pytest.mark.parametrize("n", [5, 7])
+@pytest.mark.parametrize("agg", AGGS)
+def test_large_derivative_kernels_exact_on_planes(n, agg):
+    """Rows w_a d (w_a >= 0, d an antisymmetric profile) differentiate an
+    affine s exactly: G_u = s_u F sum(w) with F = sum_b d_b (b - R), and
+    K_y = K_x^T gives the same factor in v, so plane normals are exact and
+    n'.p = F sum(w) on the plane."""
+    rng = np.random.default_rng(19 + n)
+    H, W, K = 30, 40, (45.0, 47.0, 19.5, 14.5)
+    R = n // 2
+    for pn, b in _random_planes(31 + n, 3, H, W, K):
+        z = _plane_depth(pn, b, H, W, K)
+        half = rng.uniform(0.5, 2.0, size=R)
+        d = np.concatenate([-half[::-1], [0.0], half])   # antisymmetric
+        w = rng.uniform(0.0, 2.0, size=n)
+        kx = w[:, None] * d[None, :]
+        F = float((d * (np.arange(n) - R)).sum())
+        nrm, msk, un = oracle.estimate(z, "depth_f64", K, kx, agg, unnorm=True)
+        m = msk.astype(bool)
+        assert m.sum() == (H - 2 * R) * (W - 2 * R)
+        err = oracle.angular_error_deg(nrm, np.broadcast_to(pn[:, None, None], nrm.shape))[m]
+        assert err.max() < 1e-8
+        dot = (un * _backproject(z, K)).sum(0)[m]
+        np.testing.assert_allclose(dot, F * w.sum(), rtol=1e-9)
+
+
+@pytest.mark.parametrize("n", [5, 7])
+@pytest.mark.parametrize("agg", AGGS)
+def test_large_custom_kernels_bruteforce_exact(n, agg):
+    """Arbitrary integer 5x5 / 7x7 kernels against the rational brute force
+    on small integer images with holes and ties (depth and disparity)."""
+    rng = np.random.default_rng(37 + n)
+    Kc = (2.5, 2.5, 4.5, 4.25)
+    for t in range(3):
+        kx = rng.integers(-4, 5, size=(n, n))
+        for img in _tiny_images(700 + 10 * n + t, 2, H=n + 4, W=n + 5, holes=0.03)[:3]:
+            mask_x, _, nrm_x = exact.image(img.tolist(), Kc, kx.tolist(), agg)
+            nrm, msk = oracle.estimate(img.astype(np.uint16), "depth_u16", Kc, kx, agg)
+            assert (np.array(mask_x) == msk).all()
+            assert msk.sum() > 0 or (img == 0).any()
+            np.testing.assert_allclose(nrm, np.moveaxis(np.array(nrm_x), -1, 0), atol=1e-12)
+        img = _tiny_images(800 + n + t, 1, H=n + 3, W=n + 3, lo=2, hi=9, holes=0.0)[0]
+        mask_x, _, nrm_x = exact.image(img.tolist(), Kc, kx.tolist(), agg, disparity=True, tc=2)
+        nrm, msk = oracle.estimate(img.astype(np.float64), "disparity_f64", Kc, kx, agg, tc=2.0)
+        assert (np.array(mask_x) == msk).all() and msk.sum() == 16
+        np.testing.assert_allclose(nrm, np.moveaxis(np.array(nrm_x), -1, 0), atol=1e-12)
