@@ -316,21 +316,24 @@ __device__ __forceinline__ void make_pairs(const Row<PX> &up, const Row<PX> &lo,
     }
 }
 
-// Sorting network of 4 (5 compare-exchanges) as one instruction block.
+// Sorted order of 4 values in 8 instructions.  With l = min(c, d) and
+// h = max(c, d): the extremes are min3(a, b, l) and max3(a, b, h); the second
+// smallest is min(med3(a, b, l), h) (if h is among the two smallest, so is l,
+// and h is the answer; otherwise the two smallest lie in {a, b, l}), and the
+// second largest is max(med3(a, b, h), l) by the mirror argument.  Every
+// output is one of the inputs, so ties and infinities come out exactly.
 __device__ __forceinline__ void sort4(float &a, float &b, float &c, float &d) {
-    float oa, ob, oc, od, l1, h1, l2, h2, m1, m2;
-    asm("v_min_f32 %[l1], %[a], %[b]\n\t"
-        "v_max_f32 %[h1], %[a], %[b]\n\t"
-        "v_min_f32 %[l2], %[c], %[d]\n\t"
-        "v_max_f32 %[h2], %[c], %[d]\n\t"
-        "v_max_f32 %[m1], %[l1], %[l2]\n\t"
-        "v_min_f32 %[m2], %[h1], %[h2]\n\t"
-        "v_min_f32 %[oa], %[l1], %[l2]\n\t"
-        "v_max_f32 %[od], %[h1], %[h2]\n\t"
-        "v_min_f32 %[ob], %[m1], %[m2]\n\t"
-        "v_max_f32 %[oc], %[m1], %[m2]"
-        : [oa] "=&v"(oa), [ob] "=&v"(ob), [oc] "=&v"(oc), [od] "=&v"(od), [l1] "=&v"(l1),
-          [h1] "=&v"(h1), [l2] "=&v"(l2), [h2] "=&v"(h2), [m1] "=&v"(m1), [m2] "=&v"(m2)
+    float oa, ob, oc, od, l, h, m1, m2;
+    asm("v_min_f32 %[l], %[c], %[d]\n\t"
+        "v_max_f32 %[h], %[c], %[d]\n\t"
+        "v_min3_f32 %[oa], %[a], %[b], %[l]\n\t"
+        "v_max3_f32 %[od], %[a], %[b], %[h]\n\t"
+        "v_med3_f32 %[m1], %[a], %[b], %[l]\n\t"
+        "v_med3_f32 %[m2], %[a], %[b], %[h]\n\t"
+        "v_min_f32 %[ob], %[m1], %[h]\n\t"
+        "v_max_f32 %[oc], %[m2], %[l]"
+        : [oa] "=&v"(oa), [ob] "=&v"(ob), [oc] "=&v"(oc), [od] "=&v"(od), [l] "=&v"(l),
+          [h] "=&v"(h), [m1] "=&v"(m1), [m2] "=&v"(m2)
         : [a] "v"(a), [b] "v"(b), [c] "v"(c), [d] "v"(d));
     a = oa;
     b = ob;
@@ -339,24 +342,26 @@ __device__ __forceinline__ void sort4(float &a, float &b, float &c, float &d) {
 }
 
 // Order statistics 3 and 4 (0-based) of the union of two sorted quads
-// a0 <= .. <= a3 and b0 <= .. <= b3: the k-th smallest of the union is the
-// minimum over i + j = k + 1 of max(a_i, b_j) (1-based, a_0 = b_0 = -inf,
-// a_5 = b_5 = +inf).
+// a0 <= .. <= a3 and b0 <= .. <= b3.  The k-th smallest (1-based) of the
+// union is the minimum over i + j = k of max(a_i, b_j) (1-based indices,
+// a_0 = b_0 = -inf), so
+//   x3 = min(b3, max(a0, b2), max(a1, b1), max(a2, b0), a3),
+//   x4 = min(max(a0, b3), max(a1, b2), max(a2, b1), max(a3, b0)).
+// For p <= P and q <= Q, min(max(p, Q), max(P, q)) = max(min(P, Q), max(p, q))
+// = med3(P, Q, max(p, q)) (max(p, q) <= max(P, Q)); the two pairs of x4's
+// terms then reuse max(a0, b2) and max(a2, b0) from x3: 8 instructions.
 __device__ __forceinline__ void middle_pair(const float (&t)[8], float &x3, float &x4) {
-    float p, q, r, u, v, w, y, z;
+    float p, q, r, g, h;
     asm("v_max_f32 %[p], %[a0], %[b2]\n\t"
         "v_max_f32 %[q], %[a1], %[b1]\n\t"
         "v_max_f32 %[r], %[a2], %[b0]\n\t"
-        "v_min3_f32 %[p], %[b3], %[p], %[q]\n\t"
-        "v_min3_f32 %[x3], %[p], %[r], %[a3]\n\t"
-        "v_max_f32 %[u], %[a0], %[b3]\n\t"
-        "v_max_f32 %[v], %[a1], %[b2]\n\t"
-        "v_max_f32 %[w], %[a2], %[b1]\n\t"
-        "v_max_f32 %[y], %[a3], %[b0]\n\t"
-        "v_min_f32 %[z], %[w], %[y]\n\t"
-        "v_min3_f32 %[x4], %[u], %[v], %[z]"
+        "v_min3_f32 %[q], %[b3], %[p], %[q]\n\t"
+        "v_min3_f32 %[x3], %[q], %[r], %[a3]\n\t"
+        "v_med3_f32 %[g], %[a1], %[b3], %[p]\n\t"
+        "v_med3_f32 %[h], %[a3], %[b1], %[r]\n\t"
+        "v_min_f32 %[x4], %[g], %[h]"
         : [x3] "=&v"(x3), [x4] "=&v"(x4), [p] "=&v"(p), [q] "=&v"(q), [r] "=&v"(r),
-          [u] "=&v"(u), [v] "=&v"(v), [w] "=&v"(w), [y] "=&v"(y), [z] "=&v"(z)
+          [g] "=&v"(g), [h] "=&v"(h)
         : [a0] "v"(t[0]), [a1] "v"(t[1]), [a2] "v"(t[2]), [a3] "v"(t[3]), [b0] "v"(t[4]),
           [b1] "v"(t[5]), [b2] "v"(t[6]), [b3] "v"(t[7]));
 }
