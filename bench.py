@@ -551,6 +551,22 @@ def main():
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
                          "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
                          "algorithmic_bytes_per_launch": bytes_per_launch}}
+        # wider filters (the LDS-tiled kernel): separable smoothing x derivative
+        wide = {5: ([1.0, 4.0, 6.0, 4.0, 1.0], [-1.0, -2.0, 0.0, 2.0, 1.0]),
+                7: ([1.0, 6.0, 15.0, 20.0, 15.0, 6.0, 1.0], [-1.0, -4.0, -5.0, 0.0, 5.0, 4.0, 1.0])}
+        for n, (smooth, deriv) in wide.items():
+            log("custom %dx%d gradient kernel on the same batches" % (n, n))
+            cctx.set_gradient_kernel([[a * b for b in deriv] for a in smooth])
+            wall_w, ev_w = time_launches(torch, step_cus, max(args.warmup // 3, 5), csteps)
+            gbs = bytes_per_launch / (ev_w / csteps) / 1e9
+            res["custom%d_kernel_batch" % n] = {
+                "workload": "batch64_480x640_f32depth_custom%dx%d_%s" % (n, n, args.agg),
+                "kernel": "K_x = %s (column) x %s (row)" % (smooth, deriv),
+                "us_per_launch": round(ev_w / csteps * 1e6, 2),
+                "mpix_per_s": round(px * csteps / ev_w / 1e6, 1),
+                "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                             "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                             "algorithmic_bytes_per_launch": bytes_per_launch}}
     if not args.no_packed:
         log("packed colour + normals on the same batches")
         rgbs = [torch.randint(0, 256, (B, H, W, 4), dtype=torch.uint8, device="cuda")

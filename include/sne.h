@@ -94,11 +94,11 @@ typedef struct {
 #define SNE_GRAD_SOBEL 1
 #define SNE_GRAD_SCHARR 2
 #define SNE_GRAD_PREWITT 3
-/* Any 3x3 K_x (K_y = K_x^T), set on the context with
- * sne_set_gradient_kernel: the paper searches 3x3 kernel weights by brute
- * force (Sec. IV-B).  Single frames and uniform batches (sne_estimate,
- * sne_estimate_uniform) with a context, strict rule only; other calls return
- * SNE_ERR_UNSUPPORTED. */
+/* Any 3x3, 5x5 or 7x7 K_x (K_y = K_x^T), set on the context with
+ * sne_set_gradient_kernel(_n): the paper searches 3x3 kernel weights by brute
+ * force (Sec. IV-B) and compares filters of several sizes (Fig. 2).  Single
+ * frames and uniform batches (sne_estimate, sne_estimate_uniform) with a
+ * context, strict rule only; other calls return SNE_ERR_UNSUPPORTED. */
 #define SNE_GRAD_CUSTOM 4
 
 /* Filter 3 (Phi of eq. nx2_ny2_nz2). */
@@ -167,6 +167,17 @@ int sne_estimate_rgbn(sne_ctx *ctx, const void *in, int32_t B, int32_t H, int32_
  * K[a][2] (s_+ - s_0) - K[a][0] (s_0 - s_-) + (K[a][0] + K[a][1] + K[a][2]) s_0
  * with the differences of 1/z formed from raw-value differences. */
 int sne_set_gradient_kernel(sne_ctx *ctx, const float kx[9]);
+
+/* The same for an n x n K_x, n = 3, 5 or 7 (kx[n*n], row-major, rows v-R..v+R
+ * and columns u-R..u+R with R = n/2, finite; K_y = K_x^T); n = 3 is
+ * sne_set_gradient_kernel.  With n = 5 or 7 only the gradient filters widen:
+ * the neighbourhood of n_z stays the 8-connected one, and a pixel is kept iff
+ * its whole n x n window lies inside the frame and is valid (its mask is 0
+ * otherwise, normal +0).  Each tap is formed as
+ * K[a][b] (s_ab - s_c) with s_ab - s_c = (z_c - z_ab) s_ab s_c (disparity:
+ * d_ab - d_c), plus (sum of all weights) s_c.  SNE_ERR_ARG for another n, a
+ * NULL pointer or a non-finite weight. */
+int sne_set_gradient_kernel_n(sne_ctx *ctx, int n, const float *kx);
 
 /* Descriptor of one frame of an uneven batch (all device pointers). */
 typedef struct {

@@ -153,6 +153,15 @@ hipError_t launch_uniform(const Variant &v, const UniformArgs &a, int grid, hipS
     }
 }
 
+hipError_t launch_wide(const Variant &v, const WideArgs &a, hipStream_t s) {
+    switch (base_kind(v.kind)) {
+    case SNE_DEPTH_F32: return launch_wide_f32(v, a, s);
+    case SNE_DEPTH_U16: return launch_wide_u16(v, a, s);
+    case SNE_DEPTH_F16: return launch_wide_f16(v, a, s);
+    default: return launch_wide_disp(v, a, s);
+    }
+}
+
 hipError_t launch_batch(const Variant &v, const BatchArgs &a, int grid, hipStream_t s) {
     switch (base_kind(v.kind)) {
     case SNE_DEPTH_F32: return launch_batch_f32(v, a, grid, s);
@@ -289,6 +298,28 @@ int uniform_impl(sne_ctx *ctx, const void *in, int32_t B, int32_t H, int32_t W, 
         (packed && (H + 2) * rgb->pitch >= INT32_MAX))
         return SNE_ERR_UNSUPPORTED;
     Variant v{kind, grad, agg, packed ? (int)OUT_RGBN : out_type, 1};
+    if (custom && ctx->custom_n > 3) {
+        // a 5x5 or 7x7 filter: the LDS-tiled kernel, one block per 64 x 16 tile
+        WideArgs w;
+        w.f = make_desc(in, normals, mask, H, W, in_pitch, out_pitch, mask_pitch, *K);
+        w.in_fstride = in_fs;
+        w.out_fstride = out_fs;
+        w.mask_fstride = mask_fs;
+        w.ntx = (W + kWideTW - 1) / kWideTW;
+        w.nty = (H + kWideTH - 1) / kWideTH;
+        const int64_t nb = (int64_t)B * w.ntx * w.nty;
+        if (nb > INT32_MAX) return SNE_ERR_BUDGET;
+        w.nblocks = (int32_t)nb;
+        w.R = ctx->custom_n / 2;
+        double sum = 0.0;
+        for (int i = 0; i < kWideMaxN * kWideMaxN; ++i) {
+            w.kx[i] = i < ctx->custom_n * ctx->custom_n ? ctx->custom_kx[i] : 0.f;
+            sum += (double)w.kx[i];
+        }
+        w.ksum = (float)sum;
+        if (hipSetDevice(ctx->device) != hipSuccess) return SNE_ERR_HIP;
+        return launch_wide(v, w, (hipStream_t)stream) == hipSuccess ? SNE_OK : SNE_ERR_HIP;
+    }
     int pxmax = max_px(in, normals, mask, W, in_pitch, packed ? 8 * out_pitch : out_pitch,
                        mask_pitch, in_fs, out_fs, mask_fs, packed ? 8 * plane : plane, kind,
                        packed ? SNE_OUT_F16 : out_type);
@@ -647,13 +678,19 @@ int sne_estimate_uniform(sne_ctx *ctx, const void *in, int32_t B, int32_t H, int
                         stream, nullptr);
 }
 
-int sne_set_gradient_kernel(sne_ctx *ctx, const float kx[9]) {
-    if (!ctx || !kx) return SNE_ERR_ARG;
-    for (int i = 0; i < 9; ++i)
+int sne_set_gradient_kernel_n(sne_ctx *ctx, int n, const float *kx) {
+    if (!ctx || !kx || (n != 3 && n != 5 && n != 7)) return SNE_ERR_ARG;
+    for (int i = 0; i < n * n; ++i)
         if (!std::isfinite(kx[i])) return SNE_ERR_ARG;
-    std::memcpy(ctx->custom_kx, kx, sizeof ctx->custom_kx);
+    std::memset(ctx->custom_kx, 0, sizeof ctx->custom_kx);
+    std::memcpy(ctx->custom_kx, kx, sizeof(float) * n * n);
+    ctx->custom_n = n;
     ctx->has_custom = true;
     return SNE_OK;
+}
+
+int sne_set_gradient_kernel(sne_ctx *ctx, const float kx[9]) {
+    return sne_set_gradient_kernel_n(ctx, 3, kx);
 }
 
 int sne_estimate_rgbn(sne_ctx *ctx, const void *in, int32_t B, int32_t H, int32_t W,

@@ -16,7 +16,7 @@
 
 namespace sne {
 
-constexpr int kVersion = 10200;  // 1.2.0
+constexpr int kVersion = 10300;  // 1.3.0
 // Tile-shape cache entries carry the version of the kernels they were timed
 // on; it changes only when the kernels' speed characteristics do.
 constexpr int kTileCacheVersion = 10100;
@@ -130,9 +130,10 @@ struct sne_ctx {
     void *noalloc_table = nullptr;
     void *noalloc_stage = nullptr;
     hipEvent_t noalloc_copied = nullptr;
-    // SNE_GRAD_CUSTOM: K_x row-major, once set
+    // SNE_GRAD_CUSTOM: K_x row-major (custom_n x custom_n: 3, 5 or 7), once set
     bool has_custom = false;
-    float custom_kx[9] = {};
+    int custom_n = 0;
+    float custom_kx[49] = {};
 };
 
 namespace sne {

@@ -59,6 +59,20 @@ struct UniformArgs {
     GradW gw;
 };
 
+// Wide custom gradient filters: a (2R+1)x(2R+1) K_x (R = 2, 3; K_y = K_x^T)
+// over a uniform batch, one block per 64 x 16 output tile of a frame.
+constexpr int kWideTW = 64, kWideTH = 16;  // output tile; 4 rows per thread
+constexpr int kWideMaxN = 7;
+struct WideArgs {
+    FrameDesc f;
+    int64_t in_fstride, out_fstride, mask_fstride;  // elements
+    int32_t ntx, nty;                               // tiles per frame, x and y
+    int32_t nblocks;                                // B * ntx * nty
+    int32_t R;                                      // 2 or 3
+    float kx[kWideMaxN * kWideMaxN];                // K_x row-major, (2R+1)^2 used
+    float ksum;                                     // sum of all weights
+};
+
 // Uneven batch.  Its tables are one block of device memory that the host
 // fills in pinned staging and copies over whole, so the copy also resets the
 // tile queues:
@@ -128,6 +142,10 @@ hipError_t launch_uniform_f32(const Variant &v, const UniformArgs &a, int grid, 
 hipError_t launch_uniform_u16(const Variant &v, const UniformArgs &a, int grid, hipStream_t s);
 hipError_t launch_uniform_f16(const Variant &v, const UniformArgs &a, int grid, hipStream_t s);
 hipError_t launch_uniform_disp(const Variant &v, const UniformArgs &a, int grid, hipStream_t s);
+hipError_t launch_wide_f32(const Variant &v, const WideArgs &a, hipStream_t s);
+hipError_t launch_wide_u16(const Variant &v, const WideArgs &a, hipStream_t s);
+hipError_t launch_wide_f16(const Variant &v, const WideArgs &a, hipStream_t s);
+hipError_t launch_wide_disp(const Variant &v, const WideArgs &a, hipStream_t s);
 hipError_t launch_batch_f32(const Variant &v, const BatchArgs &a, int grid, hipStream_t s);
 hipError_t launch_batch_u16(const Variant &v, const BatchArgs &a, int grid, hipStream_t s);
 hipError_t launch_batch_f16(const Variant &v, const BatchArgs &a, int grid, hipStream_t s);

@@ -842,6 +842,153 @@ __global__ __launch_bounds__(kBlock) SNE_OCCUPANCY void sne_uniform_kernel(Unifo
                                                 a.rows, a.gw);
 }
 
+// ------------------------------------------------ wide custom gradient filters
+// A (2R+1)x(2R+1) custom K_x (R = 2, 3; K_y = K_x^T) reads R samples on each
+// side, more than the three-row register window holds.  One block stages a
+// 64 x 16 output tile and its R-wide apron in LDS as (z, s) pairs (z = 0
+// where invalid or outside the frame), then each thread takes a column of 4
+// pixels.  The taps are formed against one reference sample of the column
+// (its second pixel, inside the window of every pixel of the column):
+// sum_ab K_ab s_ab = sum_ab K_ab (s_ab - s_r) + (sum K) s_r, with
+// s_ab - s_r = (z_r - z_ab) s_ab s_r from a raw-value difference (for
+// disparity d_ab - d_r), so each sample's difference serves all 4 pixels:
+//   G = s_r (sum_ab K_ab (z_r - z_ab) s_ab + sum K)      (depth)
+//   G = sum_ab K_ab (d_ab - d_r) + (sum K) d_r            (disparity)
+// The neighbourhood of n_z stays the 8-connected one, and a pixel is kept iff
+// its whole (2R+1)x(2R+1) window is inside the frame and valid.
+template <int KIND, int R, int AGG, int OUT>
+__global__ __launch_bounds__(kBlock) void sne_wide_kernel(WideArgs a) {
+    constexpr int N = 2 * R + 1, LW = kWideTW + 2 * R, LH = kWideTH + 2 * R;
+    constexpr int RPT = kWideTH / kWavesPerBlock;  // rows per thread
+    static_assert(RPT * kWavesPerBlock == kWideTH && kWideTW == kWave, "tile shape");
+    static_assert(RPT >= 2 && RPT - 2 <= R, "the reference is in every pixel's window");
+    __shared__ float2 T[LH * LW];  // (z, s)
+    using IT = typename Raw<KIND>::T;
+    using OT = typename Out<OUT>::T;
+    const int blk = (int)blockIdx.x;
+    if (blk >= a.nblocks) return;
+    const int per_frame = a.ntx * a.nty;
+    const int frame = blk / per_frame;
+    const int rem = blk - frame * per_frame;
+    const int ty = rem / a.ntx;
+    const int x0 = (rem - ty * a.ntx) * kWideTW, y0 = ty * kWideTH;
+    FrameDesc f = a.f;
+    f.in = static_cast<const IT *>(a.f.in) + frame * a.in_fstride;
+    f.out = static_cast<OT *>(a.f.out) + frame * a.out_fstride;
+    if (f.mask) f.mask = a.f.mask + frame * a.mask_fstride;
+    const int esz = (int)sizeof(IT);
+    const InBuf ib = make_inbuf(f.in, f.in_pitch, f.H, esz);
+    const int lane = (int)threadIdx.x & (kWave - 1), wv = (int)(threadIdx.x >> 6);
+
+    // stage row by row (wavefront wv takes rows wv, wv + 4, ...): lane l holds
+    // column x0 - R + l, lanes below 2R also the apron column x0 + 64 - R + l;
+    // samples outside the frame read as 0 (invalid)
+    const int gx0 = x0 - R + lane, gx1 = gx0 + kWave;
+    const int off0 = gx0 >= 0 && gx0 < f.W ? gx0 * esz : kOOB;
+    const int off1 = lane < 2 * R && gx1 < f.W ? gx1 * esz : kOOB;
+    for (int row = wv; row < LH; row += kWavesPerBlock) {
+        const int gy = y0 - R + row;
+        const bool yin = gy >= 0 && gy < f.H;
+        const int rowb = yin ? gy * ib.pitch_bytes : 0;
+        const float z0 = Raw<KIND>::value(
+            buf_load<IT, 1>(ib, yin && off0 != kOOB ? rowb + off0 : kOOB).v[0]);
+        T[row * LW + lane] = make_float2(z0, KIND == KIND_DISP ? z0 : rcp(z0));
+        if (lane < 2 * R) {
+            const float z1 = Raw<KIND>::value(
+                buf_load<IT, 1>(ib, yin && off1 != kOOB ? rowb + off1 : kOOB).v[0]);
+            T[row * LW + kWave + lane] = make_float2(z1, KIND == KIND_DISP ? z1 : rcp(z1));
+        }
+    }
+    __syncthreads();
+
+    const int top = wv * RPT;  // LDS row of pixel 0's window top
+    const int x = x0 + lane;
+    const float2 ref = T[(top + 1 + R) * LW + lane + R];  // pixel 1 of the column
+    float gu[RPT], gv[RPT], mn[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        gu[i] = 0.f;
+        gv[i] = 0.f;
+        mn[i] = kInf;
+    }
+    // window row ar feeds pixel i as its filter row ar - i
+#pragma unroll
+    for (int ar = 0; ar < RPT + 2 * R; ++ar) {
+        float zv[N], d[N];
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+            const float2 t = T[(top + ar) * LW + lane + b];
+            zv[b] = t.x;
+            d[b] = KIND == KIND_DISP ? t.y - ref.y : (ref.x - t.x) * t.y;
+        }
+        float rmin = vmin3(zv[0], zv[1], zv[2]);
+#pragma unroll
+        for (int b = 3; b < N; b += 2)
+            rmin = b + 1 < N ? vmin3(rmin, zv[b], zv[b + 1]) : vmin(rmin, zv[b]);
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            const int ka = ar - i;
+            if (ka < 0 || ka > 2 * R) continue;
+            mn[i] = vmin(mn[i], rmin);
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+                gu[i] = fmaf(a.kx[ka * N + b], d[b], gu[i]);
+                gv[i] = fmaf(a.kx[b * N + ka], d[b], gv[i]);
+            }
+        }
+    }
+
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        const int y = y0 + top + i;
+        const int c = (top + i + R) * LW + lane + R;  // LDS index of the pixel
+        const float z0 = T[c].x;
+        float Gu, Gv;
+        if constexpr (KIND == KIND_DISP) {
+            Gu = fmaf(a.ksum, ref.y, gu[i]);
+            Gv = fmaf(a.ksum, ref.y, gv[i]);
+        } else {
+            Gu = ref.y * (gu[i] + a.ksum);
+            Gv = ref.y * (gv[i] + a.ksum);
+        }
+        const bool valid = mn[i] > 0.f;
+        // slots: E, W, S, N, SE, NW, SW, NE
+        const float zj[8] = {T[c + 1].x,      T[c - 1].x,      T[c + LW].x,     T[c - LW].x,
+                             T[c + LW + 1].x, T[c - LW - 1].x, T[c + LW - 1].x, T[c - LW + 1].x};
+        float rj[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) rj[j] = rcp(zj[j] - z0);
+        const float fu = (float)x - f.u0, fv = (float)y - f.v0;
+        const float B = fmaf(fu, Gu, fv * Gv);
+        const float Spp = Gu + Gv, Spm = Gu - Gv;
+        const float Nj[8] = {Gu, -Gu, Gv, -Gv, Spp, -Spp, -Spm, Spm};
+        bool general = true;
+        if constexpr (!kTieHeavy<KIND>) {
+            const float rmax = vmax8abs(rj[0], rj[1], rj[2], rj[3], rj[4], rj[5], rj[6], rj[7]);
+            general = __builtin_amdgcn_ballot_w64(valid && !(rmax < kInf)) != 0;
+        }
+        const float phi = (AGG == AGG_MEAN) ? mean8<KIND, false>(Nj, rj, zj, z0, general)
+                                            : median8<KIND, false>(Nj, rj, zj, z0, general);
+        const float nx = f.fx * Gu, ny = f.fy * Gv, nz = B + phi;
+        const float n2 = fmaf(nx, nx, fmaf(ny, ny, nz * nz));
+        const bool deg = !(n2 > 0.f);
+        const float inv = __builtin_amdgcn_rsqf(n2);
+        const bool keep = valid && !deg;
+        const OT ox = Out<OUT>::cvt(keep ? -nx * inv : 0.f);
+        const OT oy = Out<OUT>::cvt(keep ? -ny * inv : 0.f);
+        const OT oz = Out<OUT>::cvt(keep ? nz * inv : (valid ? -1.f : 0.f));
+        if (x < f.W && y < f.H) {
+            char *o = static_cast<char *>(f.out);
+            const int64_t plane = f.out_plane * (int64_t)sizeof(OT);
+            const int64_t off = ((int64_t)y * f.out_pitch + x) * (int64_t)sizeof(OT);
+            store_stream(o + off, ox);
+            store_stream(o + plane + off, oy);
+            store_stream(o + 2 * plane + off, oz);
+            if (f.mask) store_stream(f.mask + (int64_t)y * f.mask_pitch + x, (uint8_t)valid);
+        }
+    }
+}
+
 // A value loaded through a generic pointer counts as lane-varying for the
 // compiler, even at a wave-uniform address.  The batch tables are only read
 // at wave-uniform addresses: moving every dword to a scalar register keeps
@@ -1014,6 +1161,30 @@ hipError_t uniform_variant(const Variant &v, const UniformArgs &a, int grid, hip
     }
     return SNE_DISPATCH(uniform_px, KIND, v, a, grid, s);
 }
+template <int KIND, int R>
+hipError_t wide_r(const Variant &v, const WideArgs &a, hipStream_t s) {
+    const dim3 grid((unsigned)a.nblocks), block(kBlock);
+    if (v.agg == AGG_MEAN) {
+        if (v.out == OUT_F32)
+            hipLaunchKernelGGL((sne_wide_kernel<KIND, R, AGG_MEAN, OUT_F32>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((sne_wide_kernel<KIND, R, AGG_MEAN, OUT_F16>), grid, block, 0, s, a);
+    } else {
+        if (v.out == OUT_F32)
+            hipLaunchKernelGGL((sne_wide_kernel<KIND, R, AGG_MEDIAN, OUT_F32>), grid, block, 0, s,
+                               a);
+        else
+            hipLaunchKernelGGL((sne_wide_kernel<KIND, R, AGG_MEDIAN, OUT_F16>), grid, block, 0, s,
+                               a);
+    }
+    return hipGetLastError();
+}
+template <int KIND>
+hipError_t wide_variant(const Variant &v, const WideArgs &a, hipStream_t s) {
+    if (a.R == 2) return wide_r<KIND, 2>(v, a, s);
+    if (a.R == 3) return wide_r<KIND, 3>(v, a, s);
+    return hipErrorInvalidValue;
+}
 template <int KIND>
 hipError_t batch_variant(const Variant &v, const BatchArgs &a, int grid, hipStream_t s) {
     return SNE_DISPATCH(batch_px, KIND, v, a, grid, s);
@@ -1039,6 +1210,10 @@ template <int KIND> hipError_t occupancy_variant(const Variant &v, int *blocks) 
 hipError_t SNE_CAT(launch_uniform_, SNE_SUFFIX)(const Variant &v, const UniformArgs &a, int grid,
                                                 hipStream_t s) {
     return uniform_variant<SNE_KIND>(v, a, grid, s);
+}
+
+hipError_t SNE_CAT(launch_wide_, SNE_SUFFIX)(const Variant &v, const WideArgs &a, hipStream_t s) {
+    return wide_variant<SNE_KIND>(v, a, s);
 }
 
 hipError_t SNE_CAT(launch_batch_, SNE_SUFFIX)(const Variant &v, const BatchArgs &a, int grid,

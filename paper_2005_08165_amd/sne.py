@@ -136,6 +136,7 @@ _SIGS = {
                            _vp], _int),
     "sne_set_intrinsics_table": ([_vp, ctypes.POINTER(Intrinsics), _i32], _int),
     "sne_set_gradient_kernel": ([_vp, ctypes.POINTER(ctypes.c_float)], _int),
+    "sne_set_gradient_kernel_n": ([_vp, _int, ctypes.POINTER(ctypes.c_float)], _int),
     "sne_estimate_batched": ([_vp, ctypes.POINTER(FrameDesc), _i32, _int, _int, _int, _int, _vp],
                              _int),
     "sne_estimate_batched_noalloc": ([_vp, ctypes.POINTER(FrameDesc), _i32, _int, _int, _int,
@@ -362,13 +363,15 @@ class Context:
         check("sne_set_intrinsics_table", lib().sne_set_intrinsics_table(self._h, arr, len(Ks)))
 
     def set_gradient_kernel(self, kx) -> None:
-        """sne_set_gradient_kernel: the 3x3 K_x (row-major) that grad="custom"
-        uses on this context (K_y = K_x^T)."""
-        vals = [float(x) for row in kx for x in row]
-        if len(vals) != 9:
-            raise ValueError("a 3x3 kernel is expected")
-        arr = (ctypes.c_float * 9)(*vals)
-        check("sne_set_gradient_kernel", lib().sne_set_gradient_kernel(self._h, arr))
+        """sne_set_gradient_kernel_n: the square K_x (row-major; 3x3, 5x5 or
+        7x7) that grad="custom" uses on this context (K_y = K_x^T)."""
+        rows = [[float(x) for x in row] for row in kx]
+        n = len(rows)
+        if any(len(r) != n for r in rows):
+            raise ValueError("a square kernel is expected")
+        vals = [x for r in rows for x in r]
+        arr = (ctypes.c_float * max(len(vals), 1))(*vals)
+        check("sne_set_gradient_kernel_n", lib().sne_set_gradient_kernel_n(self._h, n, arr))
 
     # -- compute -------------------------------------------------------------
     def estimate(self, raw: torch.Tensor, K, kind="depth_f32", grad="fd", agg="mean", out="f32",

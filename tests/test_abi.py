@@ -36,7 +36,7 @@ def test_noalloc_rejects_bad_arguments_before_the_gpu():
 
 
 def test_version_and_status_strings():
-    assert sne.version() == 10200
+    assert sne.version() == 10300
     assert sne.status_string(0) == "ok"
     assert sne.status_string(-1) == "invalid argument"
     assert sne.status_string(12345) == "unknown status"
@@ -102,6 +102,9 @@ def test_null_context_errors():
     assert L.sne_ctx_create(None, 0) == -1
     assert L.sne_get_tile(None, 0, 10, 1, 0, 0, 0, 0, ctypes.byref(t)) == -1
     assert L.sne_get_tile(None, 10, 10, 0, 0, 0, 0, 0, ctypes.byref(t)) == -1
+    kx = (ctypes.c_float * 49)()
+    assert L.sne_set_gradient_kernel(None, kx) == -1
+    assert L.sne_set_gradient_kernel_n(None, 5, kx) == -1
 
 
 def test_default_tile_shape_without_context():
