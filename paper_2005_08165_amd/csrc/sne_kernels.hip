@@ -245,6 +245,11 @@ template <int PX> struct Row {
     float hmin[PX];    // min z over columns k-1..k+1: > 0 iff all 3 valid
     float D[PX];       // s[k+1] - s[k-1] (horizontal central difference)
     float rE[PX + 1];  // rE[i] = 1 / (z[i+1] - z[i])
+    // lenient rule with a 3-row filter only: the row's horizontal gradient
+    // line at columns 1..PX and whether it has one (computed once, used by
+    // the three output rows whose window holds this row)
+    float Lh[PX];
+    bool hh[PX];
 };
 
 // Lanes at the inner edges of two half-wave tiles (31 and 32) take their
@@ -539,6 +544,14 @@ __device__ __forceinline__ float lenient_line(float zm, float z0, float zp, floa
     return (okm && okp) ? both : (ok0 && okp) ? plus : (ok0 && okm) ? minus : 0.f;
 }
 
+// The lenient horizontal lines of a finished row.
+template <int KIND, int PX> __device__ __forceinline__ void lenient_hlines(Row<PX> &o) {
+#pragma unroll
+    for (int k = 0; k < PX; ++k)
+        o.Lh[k] = lenient_line<KIND>(o.z[k], o.z[k + 1], o.z[k + 2], o.s[k], o.s[k + 1],
+                                     o.s[k + 2], o.D[k], o.hh[k]);
+}
+
 // Lenient G from its lines (centre line c, side lines a and b, each 0 when
 // missing): the strict combination of the available lines, rescaled to the
 // full filter's weight.  With every line present it is the strict value.
@@ -568,7 +581,9 @@ __device__ __forceinline__ void tile_row(const FrameDesc &f, const InBuf &ib, co
                                          const RowState<PX> &prev, RowState<PX> &cur,
                                          RowState<PX> &next) {
     constexpr bool FD = GK == GK_FD;
+    constexpr bool LENR = LEN && GK != GK_CUSTOM;  // the lenient rule applies
     finish_row<KIND, PX, HALF>(pend, next.row, e);
+    if constexpr (LENR && !FD) lenient_hlines<KIND, PX>(next.row);
     load_raw<KIND, PX>(ib, r + 1 + SNE_PREFETCH_ROWS, col_off, halo_off, pend);  // prefetch
     // packed output: this row's RGBX bytes, in flight while the row is
     // computed (a frame without colour has an empty resource: zeros)
@@ -592,6 +607,27 @@ __device__ __forceinline__ void tile_row(const FrameDesc &f, const InBuf &ib, co
             V[i] = rn.z[i] - rp.z[i];
         else
             V[i] = (rp.z[i] - rn.z[i]) * (rp.s[i] * rn.s[i]);
+    }
+
+    // lenient rule: when a valid pixel of this row somewhere in the
+    // wavefront lacks a full window, its vertical lines at columns 0..PX+1
+    // (each used by three pixels; the horizontal ones come with the rows)
+    bool lenient_path = false;
+    float VL[PX + 2];
+    bool VH[PX + 2];
+    if constexpr (LENR && !FD) {
+        bool need = false;
+#pragma unroll
+        for (int k = 0; k < PX; ++k)
+            need = need ||
+                   (!(vmin3(rp.hmin[k], rc.hmin[k], rn.hmin[k]) > 0.f) && rc.z[k + 1] > 0.f);
+        if (__builtin_amdgcn_ballot_w64(need) != 0) {
+            lenient_path = true;
+#pragma unroll
+            for (int i = 0; i < PX + 2; ++i)
+                VL[i] = lenient_line<KIND>(rp.z[i], rc.z[i], rn.z[i], rp.s[i], rc.s[i], rn.s[i],
+                                           V[i], VH[i]);
+        }
     }
 
     using OT = typename Out<OUT>::T;
@@ -629,33 +665,31 @@ __device__ __forceinline__ void tile_row(const FrameDesc &f, const InBuf &ib, co
             Gu = fmaf(gw.wa, rp.D[k] + rn.D[k], rc.D[k]);
             Gv = fmaf(gw.wa, V[c - 1] + V[c + 1], V[c]);
         }
-        bool lenient_wave = false;
-        if constexpr (LEN && GK != GK_CUSTOM) {
-            // a valid pixel without a full window somewhere in the wavefront
+        // with every line present the lenient G is the strict one, bit for
+        // bit, so pixels with a full window may take either path
+        if constexpr (LENR && FD) {
+            // FD has one line per direction: decided per column position,
+            // nothing shared
             if (__builtin_amdgcn_ballot_w64(!valid && zc > 0.f) != 0) {
-                lenient_wave = true;
-                bool hp = false, hc, hn = false, du, dv;
-                float Lp = 0.f, Ln = 0.f;
+                lenient_path = true;
+                bool hc, vc;
                 const float Lc = lenient_line<KIND>(rc.z[c - 1], zc, rc.z[c + 1], rc.s[c - 1],
                                                     rc.s[c], rc.s[c + 1], rc.D[k], hc);
-                if constexpr (!FD) {
-                    Lp = lenient_line<KIND>(rp.z[c - 1], rp.z[c], rp.z[c + 1], rp.s[c - 1],
-                                            rp.s[c], rp.s[c + 1], rp.D[k], hp);
-                    Ln = lenient_line<KIND>(rn.z[c - 1], rn.z[c], rn.z[c + 1], rn.s[c - 1],
-                                            rn.s[c], rn.s[c + 1], rn.D[k], hn);
-                }
-                Gu = lenient_combine<FD>(Lc, hc, Lp, hp, Ln, hn, gw, du);
-                bool vl = false, vr = false, vc;
-                float Vl = 0.f, Vr = 0.f;
                 const float Vc = lenient_line<KIND>(rp.z[c], zc, rn.z[c], rp.s[c], rc.s[c],
                                                     rn.s[c], V[c], vc);
-                if constexpr (!FD) {
-                    Vl = lenient_line<KIND>(rp.z[c - 1], rc.z[c - 1], rn.z[c - 1], rp.s[c - 1],
-                                            rc.s[c - 1], rn.s[c - 1], V[c - 1], vl);
-                    Vr = lenient_line<KIND>(rp.z[c + 1], rc.z[c + 1], rn.z[c + 1], rp.s[c + 1],
-                                            rc.s[c + 1], rn.s[c + 1], V[c + 1], vr);
-                }
-                Gv = lenient_combine<FD>(Vc, vc, Vl, vl, Vr, vr, gw, dv);
+                Gu = Lc;
+                Gv = Vc;
+                valid = zc > 0.f && hc && vc;
+            } else {
+                lenient_path = false;
+            }
+        } else if constexpr (LENR) {
+            if (lenient_path) {
+                bool du, dv;
+                Gu = lenient_combine<FD>(rc.Lh[k], rc.hh[k], rp.Lh[k], rp.hh[k], rn.Lh[k],
+                                         rn.hh[k], gw, du);
+                Gv = lenient_combine<FD>(VL[c], VH[c], VL[c - 1], VH[c - 1], VL[c + 1],
+                                         VH[c + 1], gw, dv);
                 valid = zc > 0.f && du && dv;
             }
         }
@@ -675,7 +709,7 @@ __device__ __forceinline__ void tile_row(const FrameDesc &f, const InBuf &ib, co
         // (signs do not matter here: the raw pair values are used)
         bool general = true;
         if constexpr (!kTieHeavy<KIND>) {
-            if (!lenient_wave) {
+            if (!lenient_path) {
                 const float rmax = vmax8abs(rc.rE[c], rc.rE[c - 1], pd.rS[k], pu.rS[k],
                                             pd.rSE[c], pu.rSE[k], pd.rSW[k], pu.rSW[c]);
                 const bool any_drop = !(rmax < kInf);
@@ -775,6 +809,10 @@ __device__ __forceinline__ void run_tile(const FrameDesc &f, int c0, int r0, int
     finish_row<KIND, PX, HALF>(p0, A.row, e);
     load_raw<KIND, PX>(ib, rb, col_off, halo_off, p0);
     finish_row<KIND, PX, HALF>(p0, B.row, e);
+    if constexpr (LEN && GK == GK_3ROW) {  // the lenient rule's shared horizontal lines
+        lenient_hlines<KIND, PX>(A.row);
+        lenient_hlines<KIND, PX>(B.row);
+    }
     make_pairs<PX>(A.row, B.row, A.below);
     load_raw<KIND, PX>(ib, rb + 1, col_off, halo_off, p0);
 #define SNE_ROW(I, P, X, Y, Z)                                                                  \
