@@ -827,19 +827,23 @@ __device__ __forceinline__ void run_tile(const FrameDesc &f, int c0, int r0, int
         SNE_ROW(i + 2, p0, C, A, B);
     }
 #else
-    // two rows in flight: p0 and p1 alternate; after three rows (the period
-    // of the window roles) their roles swap by copy
+    // two rows in flight: p0 and p1 alternate; the loop covers six rows (the
+    // common period of the window roles and the two load buffers), so no
+    // buffer is ever copied (a copy would wait for its load)
     RawRow<KIND, PX> p1;
     load_raw<KIND, PX>(ib, rb + 2, col_off, halo_off, p1);
-    for (int i = 0; i < n; i += 3) {
+    for (int i = 0; i < n; i += 6) {
         SNE_ROW(i, p0, A, B, C);
         if (i + 1 >= n) break;
         SNE_ROW(i + 1, p1, B, C, A);
         if (i + 2 >= n) break;
         SNE_ROW(i + 2, p0, C, A, B);
-        const RawRow<KIND, PX> t = p0;
-        p0 = p1;
-        p1 = t;
+        if (i + 3 >= n) break;
+        SNE_ROW(i + 3, p1, A, B, C);
+        if (i + 4 >= n) break;
+        SNE_ROW(i + 4, p0, B, C, A);
+        if (i + 5 >= n) break;
+        SNE_ROW(i + 5, p1, C, A, B);
     }
 #endif
 #undef SNE_ROW
