@@ -73,15 +73,15 @@ static double angle_deg(const double *a, const double *b) {
 // One frame through sne_estimate; outputs copied back to the host.
 static void run_single(sne_ctx *ctx, const std::vector<float> &z, int H, int W,
                        const sne_intrinsics &K, hipStream_t st, std::vector<float> &nrm,
-                       std::vector<uint8_t> &msk, int flags = 0) {
+                       std::vector<uint8_t> &msk, int flags = 0, int grad = SNE_GRAD_SOBEL) {
     float *d_in, *d_n;
     uint8_t *d_m;
     HIPOK(hipMalloc(&d_in, z.size() * 4));
     HIPOK(hipMalloc(&d_n, 3 * z.size() * 4));
     HIPOK(hipMalloc(&d_m, z.size()));
     HIPOK(hipMemcpy(d_in, z.data(), z.size() * 4, hipMemcpyHostToDevice));
-    CHECK(sne_estimate(ctx, d_in, H, W, W, &K, SNE_DEPTH_F32 | flags, SNE_GRAD_SOBEL,
-                       SNE_AGG_MEDIAN, SNE_OUT_F32, d_n, W, d_m, W, st) == SNE_OK);
+    CHECK(sne_estimate(ctx, d_in, H, W, W, &K, SNE_DEPTH_F32 | flags, grad, SNE_AGG_MEDIAN,
+                       SNE_OUT_F32, d_n, W, d_m, W, st) == SNE_OK);
     HIPOK(hipStreamSynchronize(st));
     nrm.resize(3 * z.size());
     msk.resize(z.size());
@@ -131,6 +131,41 @@ int main() {
         CHECK(nvalid > P / 2);
         std::printf("single frame (%s rule): %zu valid, mean %.2e deg, max %.2e deg\n",
                     rule ? "lenient" : "strict", nvalid, sum / nvalid, mx);
+        CHECK(sum / nvalid <= 0.01 && mx <= 0.1);
+    }
+
+    // 1b. a custom 5x5 gradient kernel (the LDS-tiled path) against the oracle
+    {
+        float kx[25];
+        double kxd[25];
+        const float sm[5] = {1, 4, 6, 4, 1}, dv[5] = {-1, -2, 0, 2, 1};
+        for (int a = 0; a < 5; ++a)
+            for (int b = 0; b < 5; ++b) kxd[5 * a + b] = kx[5 * a + b] = sm[a] * dv[b];
+        CHECK(sne_set_gradient_kernel_n(ctx, 4, kx) == SNE_ERR_ARG);
+        CHECK(sne_set_gradient_kernel_n(ctx, 5, kx) == SNE_OK);
+        std::vector<float> nrm;
+        std::vector<uint8_t> msk;
+        run_single(ctx, z, H, W, K, st, nrm, msk, 0, SNE_GRAD_CUSTOM);
+        std::vector<double> on(3 * (size_t)H * W);
+        std::vector<unsigned char> om((size_t)H * W);
+        CHECK(orc_estimate(z.data(), 0, H, W, W, K.fx, K.fy, K.u0, K.v0, 1.0, 5, SNE_AGG_MEDIAN,
+                           0, kxd, on.data(), om.data(), nullptr, nullptr, 0) == 0);
+        double sum = 0, mx = 0;
+        size_t nvalid = 0;
+        const size_t P = (size_t)H * W;
+        for (size_t i = 0; i < P; ++i) {
+            CHECK(msk[i] == om[i]);
+            if (!om[i]) continue;
+            const double g[3] = {nrm[i], nrm[P + i], nrm[2 * P + i]};
+            const double o[3] = {on[i], on[P + i], on[2 * P + i]};
+            const double e = angle_deg(g, o);
+            sum += e;
+            mx = e > mx ? e : mx;
+            ++nvalid;
+        }
+        CHECK(nvalid > P / 4);
+        std::printf("single frame (custom 5x5): %zu valid, mean %.2e deg, max %.2e deg\n",
+                    nvalid, sum / nvalid, mx);
         CHECK(sum / nvalid <= 0.01 && mx <= 0.1);
     }
 
