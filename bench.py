@@ -116,40 +116,60 @@ def plain_single_frame(torch, S, sne, grad, agg, reps=200):
             "latency_us_p99": round(lat[int(len(lat) * 0.99) - 1] * 1e6, 1)}
 
 
-def disparity_batch(torch, S, sne, reps=300, warmup=30):
+def disparity_batch(torch, S, sne, reps=300, warmup=30, dense_too=True):
     """The stereo workload: one launch over 128 FP32 disparity frames of
     375x1242 (road plane and box obstacles, f = 721.5 px, 0.54 m baseline,
     1-128 px disparity, +-0.25 px uniform noise, 0 outside that range),
     Scharr gradients, median, FP32 normals + mask (17 B/px, 1.01 GB per
-    launch, four times the last-level cache)."""
+    launch, four times the last-level cache).  The frames are stored with
+    their rows padded to 1280 elements (sne_row_pitch: every row on a 256-byte
+    boundary); the same frames stored densely (pitch 1242) are timed too."""
     B = 128
     cam = S.ROAD_CAM
-    raw = torch.stack([S.make_road(2000 + i, cam, device="cuda").raw for i in range(B)])
     H, W = cam.H, cam.W
-    nrm = torch.empty((B, 3, H, W), device="cuda")
-    msk = torch.empty((B, H, W), dtype=torch.uint8, device="cuda")
+    dense = torch.stack([S.make_road(2000 + i, cam, device="cuda").raw for i in range(B)])
     ctx = sne.Context(0)
     K = cam.as_tuple()
-    tile = ctx.get_tile(H, W, B, "disparity_f32", "scharr", "median", "f32")
-
-    def step(i):
-        sne.estimate_uniform(raw, K, "disparity_f32", "scharr", "median", normals=nrm, mask=msk,
-                             ctx=ctx)
-
-    torch.cuda.synchronize()
-    wall, ev = time_launches(torch, step, warmup, reps)
     px = B * H * W
-    gbs = px * 17 * reps / ev / 1e9
-    return {"workload": "batch128_375x1242_f32disparity_scharr_median", "frames": B,
+    out = {}
+    for layout in ("pitched", "dense") if dense_too else ("pitched",):
+        if layout == "pitched":
+            raw = sne.pitched_empty((B, H, W), torch.float32)
+            raw.copy_(dense)
+            nrm = sne.pitched_empty((B, 3, H, W), torch.float32)
+            msk = sne.pitched_empty((B, H, W), torch.uint8)
+        else:
+            raw = dense
+            nrm = torch.empty((B, 3, H, W), device="cuda")
+            msk = torch.empty((B, H, W), dtype=torch.uint8, device="cuda")
+        tile = ctx.get_tile(H, W, B, "disparity_f32", "scharr", "median", "f32",
+                            in_pitch=raw.stride(-2), out_pitch=nrm.stride(-2))
+
+        def step(i):
+            sne.estimate_uniform(raw, K, "disparity_f32", "scharr", "median", normals=nrm,
+                                 mask=msk, ctx=ctx)
+
+        torch.cuda.synchronize()
+        wall, ev = time_launches(torch, step, warmup, reps)
+        gbs = px * 17 * reps / ev / 1e9
+        workload = "batch128_375x1242_f32disparity_scharr_median"
+        if layout == "pitched":
+            workload += "_pitch%d" % raw.stride(-2)
+        out[layout] = {
+            "workload": workload, "row_pitch": raw.stride(-2), "frames": B,
             "mpix": round(px / 1e6, 2), "us_per_launch": round(ev / reps * 1e6, 2),
             "mpix_per_s": round(px * reps / ev / 1e6, 1),
             "frames_per_s": round(B * reps / ev, 1),
             "tile": {"cols_per_lane": tile[0], "rows": tile[1], "lanes": tile[2]},
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
                          "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
-                         "traffic": measured_traffic(
-                             "batch128_375x1242_f32disparity_scharr_median", tile),
+                         "traffic": measured_traffic(workload, tile),
                          "algorithmic_bytes_per_launch": px * 17}}
+        del raw, nrm, msk
+    res = out["pitched"]
+    if dense_too:
+        res["dense_layout"] = out["dense"]
+    return res
 
 
 def probe_calibration(torch, sne, px=4 * 64 * 480 * 640, reps=20):
@@ -431,6 +451,8 @@ def main():
     ap.add_argument("--no-packed", action="store_true")
     ap.add_argument("--no-custom", action="store_true")
     ap.add_argument("--disparity-steps", type=int, default=300)
+    ap.add_argument("--no-dense-disparity", action="store_true",
+                    help="time the stereo batch in the padded layout only")
     ap.add_argument("--serving-rate", type=float, default=0.0,
                     help="run the serving loop at this one offered rate (FD-mean) only")
     ap.add_argument("--autotune", action="store_true",
@@ -613,7 +635,8 @@ def main():
                                      plain_single_frame(torch, S, sne, "fd", "mean")]
     if not args.no_disparity:
         log("disparity batch (128 x 375x1242)")
-        res["disparity_batch"] = disparity_batch(torch, S, sne, reps=args.disparity_steps)
+        res["disparity_batch"] = disparity_batch(torch, S, sne, reps=args.disparity_steps,
+                                                 dense_too=not args.no_dense_disparity)
     if not args.no_uneven:
         log("uneven persistent batch")
         res["uneven_batch"] = [uneven_batch(torch, S, sne, "mean", autotune=args.autotune),

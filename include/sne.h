@@ -251,10 +251,28 @@ typedef struct {
  * back to a narrower cols_per_lane. */
 int sne_set_tile(sne_ctx *ctx, const sne_tile *tile);
 
-/* The tile shape ctx would use for a batch of B frames of H x W of this
- * variant (ctx may be NULL: the built-in heuristic). */
+/* The tile shape ctx would use for a batch of B dense frames (row pitch W)
+ * of H x W of this variant (ctx may be NULL: the built-in heuristic). */
 int sne_get_tile(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int grad, int agg,
                  int out_type, sne_tile *tile);
+
+/* Row layout.  The tile-shape cache keeps two classes of frames apart: those
+ * whose every input and normal row starts at a 256-byte boundary (base
+ * pointer, row pitch in bytes and frame stride all multiples of 256) and the
+ * others.  Unaligned rows make the cache lines at the edges of every strip of
+ * columns shared between wavefronts, which costs HBM bandwidth and favours
+ * short tiles; 128 x 375x1242 FP32 disparity frames, Scharr-median, run in
+ * 213 us dense (pitch 1242) and in 162 us at pitch 1280 on an MI355X.
+ * sne_row_pitch returns the smallest pitch (elements) >= W whose rows are
+ * 256-byte multiples, for elements of elem_bytes = 1, 2 or 4 bytes;
+ * SNE_ERR_ARG for W < 1 or another element size. */
+int64_t sne_row_pitch(int32_t W, int32_t elem_bytes);
+
+/* sne_get_tile for frames with the given input and output row pitches
+ * (elements, >= W; the buffers are taken to start at 256-byte boundaries). */
+int sne_get_tile_pitched(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int64_t in_pitch,
+                         int64_t out_pitch, int kind, int grad, int agg, int out_type,
+                         sne_tile *tile);
 
 /* Time every candidate tile shape on an H x W x B workload of this variant
  * (synthetic planar input in scratch buffers the call allocates and frees;
@@ -264,6 +282,14 @@ int sne_get_tile(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int gr
  * report it (tile may be NULL).  Synchronous; seconds at most. */
 int sne_autotune(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int grad, int agg,
                  int out_type, sne_tile *tile);
+
+/* sne_autotune on frames stored at the given input and output row pitches
+ * (elements, >= W; the mask uses the output pitch): the fastest shape is kept
+ * for the row layout of those pitches.  sne_autotune is this call with both
+ * pitches W. */
+int sne_autotune_pitched(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int64_t in_pitch,
+                         int64_t out_pitch, int kind, int grad, int agg, int out_type,
+                         sne_tile *tile);
 
 /* Time every candidate tile shape on the caller's uneven batch (the frames
  * of sne_estimate_batched, whose outputs are written by every timed launch;

@@ -119,27 +119,36 @@ TileChoice default_tile(const sne_ctx *ctx, int H, int W, int64_t B, int pxmax) 
     return best;
 }
 
+int row_layout(const void *p, int64_t row_bytes, int64_t frame_bytes) {
+    return aligned(p, kRowAlign) && row_bytes % kRowAlign == 0 && frame_bytes % kRowAlign == 0;
+}
+
 TileChoice pick_tile(const sne_ctx *ctx, int H, int W, int64_t B, const Variant &v, int pxmax,
-                     bool uneven) {
+                     bool uneven, int layout) {
     if (ctx && ctx->forced.rows > 0) {
         TileChoice t = ctx->forced;
         while (t.px > pxmax) t.px >>= 1;
         return t;
     }
     if (ctx) {
-        // an uneven batch prefers a shape tuned on the persistent kernel
-        // a shape tuned for the variant itself, else (lenient rule) the one
-        // tuned for the strict rule of the same variant
-        for (int kind : {v.kind, base_kind(v.kind)})
-            for (int bc : {uneven ? kUnevenClass : -1, batch_class(B)}) {
-                if (bc < 0) continue;
-                auto it = ctx->cache.find(TileKey{H, W, bc, kind, v.grad, v.agg, v.out});
-                if (it != ctx->cache.end()) {
-                    TileChoice t = it->second;
-                    while (t.px > pxmax) t.px >>= 1;
-                    return t;
+        // a shape tuned on this row layout, else (aligned rows) one tuned on
+        // unaligned rows; an uneven batch prefers a shape tuned on the
+        // persistent kernel; a shape tuned for the variant itself, else
+        // (lenient rule) the one tuned for the strict rule of the same variant
+        for (int lay : {layout, 0}) {
+            if (lay != layout && layout == 0) break;
+            for (int kind : {v.kind, base_kind(v.kind)})
+                for (int bc : {uneven ? kUnevenClass : -1, batch_class(B)}) {
+                    if (bc < 0) continue;
+                    auto it = ctx->cache.find(TileKey{H, W, bc, kind, v.grad, v.agg, v.out, lay});
+                    if (it != ctx->cache.end()) {
+                        TileChoice t = it->second;
+                        while (t.px > pxmax) t.px >>= 1;
+                        return t;
+                    }
                 }
-            }
+            if (layout == 0) break;
+        }
     }
     return default_tile(ctx, H, W, B, pxmax);
 }
@@ -327,7 +336,11 @@ int uniform_impl(sne_ctx *ctx, const void *in, int32_t B, int32_t H, int32_t W, 
         while (pxmax > 1 && (rgb->pitch % (4 * pxmax) || rgb_fs % (4 * pxmax) ||
                              !aligned(rgb->rgb, 4 * pxmax)))
             pxmax >>= 1;
-    TileChoice t = force ? *force : pick_tile(ctx, H, W, B, v, pxmax);
+    const int64_t orow = packed ? 16 * out_pitch : out_pitch * (int64_t)out_elem(out_type);
+    const int layout =
+        row_layout(in, in_pitch * (int64_t)in_elem(kind), in_fs * (int64_t)in_elem(kind)) &&
+        row_layout(normals, orow, out_fs * (packed ? 2 : (int64_t)out_elem(out_type)));
+    TileChoice t = force ? *force : pick_tile(ctx, H, W, B, v, pxmax, false, layout);
     // The packed pixels are 16 bytes each: with one column per lane a store
     // instruction covers 1 KiB of contiguous output, with more columns per
     // lane it scatters 16-byte pieces (measured 3.6x slower at 4 columns).
@@ -497,8 +510,9 @@ std::vector<TileChoice> tile_candidates(int H, int pxmax, bool remap_choices) {
     return cand;
 }
 
-// Every candidate is timed once (a burst of launches of about 2 ms after a
-// warm-up launch); the eight fastest are then timed again in interleaved
+// After about 0.3 s of launches that let the clocks settle, every candidate
+// is timed once (a burst of launches of about 2 ms after a warm-up launch);
+// the eight fastest are then timed again with 8 ms bursts in interleaved
 // rounds, so that a slow phase of the device does not favour whichever
 // candidate ran during it, and the best median wins.  `launch` enqueues one
 // launch of a shape on `st`.  Returns rows = 0 if nothing could be timed.
@@ -521,6 +535,11 @@ TileChoice pick_fastest(const std::vector<TileChoice> &cand, const TileChoice &p
         float ms = 0.f;
         if (time_one(probe, ms) && ms > 0.f)
             burst = (int)std::min(64.f, std::max(3.f, std::ceil(2.0f / ms)));
+        // the clocks take a few hundred ms of load to settle: about 0.3 s of
+        // the probe shape first, so the first pass compares steady-state rates
+        const int settle = ms > 0.f ? (int)std::min(400.f, std::ceil(300.f / (ms * burst))) : 0;
+        for (int i = 0; i < settle; ++i)
+            if (!time_one(probe, ms)) break;
     }
     std::vector<std::pair<float, size_t>> first;
     for (size_t i = 0; i < cand.size(); ++i) {
@@ -529,7 +548,9 @@ TileChoice pick_fastest(const std::vector<TileChoice> &cand, const TileChoice &p
     }
     std::sort(first.begin(), first.end());
     if (first.size() > 8) first.resize(8);
+    // the finalists: longer bursts (about 8 ms), interleaved rounds
     constexpr int kRounds = 7;
+    burst = std::min(256, 4 * burst);
     std::vector<std::vector<float>> rounds(first.size());
     for (int r = 0; r < kRounds; ++r)
         for (size_t j = 0; j < first.size(); ++j) {
@@ -776,33 +797,54 @@ int sne_set_tile(sne_ctx *ctx, const sne_tile *tile) {
     return SNE_OK;
 }
 
-int sne_get_tile(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int grad, int agg,
-                 int out_type, sne_tile *tile) {
-    if (!tile || H < 1 || W < 1 || B < 1 || !valid_enum(kind, grad, agg, out_type))
+int sne_get_tile_pitched(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int64_t in_pitch,
+                         int64_t out_pitch, int kind, int grad, int agg, int out_type,
+                         sne_tile *tile) {
+    if (!tile || H < 1 || W < 1 || B < 1 || in_pitch < W || out_pitch < W ||
+        !valid_enum(kind, grad, agg, out_type))
         return SNE_ERR_ARG;
     Variant v{kind, grad, agg, out_type, 1};
-    TileChoice t = pick_tile(ctx, H, W, B, v, 4);
-    tile->cols_per_lane = t.px;
-    tile->rows = t.rows;
-    tile->lanes = t.half ? 32 : 64;
+    // buffers from the allocator start at kRowAlign boundaries
+    const void *base = nullptr;
+    const int64_t ir = in_pitch * (int64_t)in_elem(kind);
+    const int64_t orow = out_pitch * (int64_t)out_elem(out_type);
+    const int layout = row_layout(base, ir, ir * H) && row_layout(base, orow, 3 * orow * H);
+    report_tile(pick_tile(ctx, H, W, B, v, 4, false, layout), tile);
     return SNE_OK;
 }
 
-
-int sne_autotune(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int grad, int agg,
+int sne_get_tile(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int grad, int agg,
                  int out_type, sne_tile *tile) {
+    return sne_get_tile_pitched(ctx, H, W, B, W, W, kind, grad, agg, out_type, tile);
+}
+
+int64_t sne_row_pitch(int32_t W, int32_t elem_bytes) {
+    if (W < 1 || !(elem_bytes == 1 || elem_bytes == 2 || elem_bytes == 4)) return SNE_ERR_ARG;
+    const int64_t per = kRowAlign / elem_bytes;  // elements per aligned unit
+    return ((int64_t)W + per - 1) / per * per;
+}
+
+
+int sne_autotune_pitched(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int64_t in_pitch,
+                         int64_t out_pitch, int kind, int grad, int agg, int out_type,
+                         sne_tile *tile) {
     if (grad == SNE_GRAD_CUSTOM) return SNE_ERR_UNSUPPORTED;
-    if (!ctx || H < 1 || W < 1 || B < 1 || !valid_enum(kind, grad, agg, out_type))
+    if (!ctx || H < 1 || W < 1 || B < 1 || in_pitch < W || out_pitch < W ||
+        !valid_enum(kind, grad, agg, out_type))
         return SNE_ERR_ARG;
+    if (!frame_fits(H, in_pitch, kind, out_pitch, out_type, out_pitch))
+        return SNE_ERR_UNSUPPORTED;
     if (hipSetDevice(ctx->device) != hipSuccess) return SNE_ERR_HIP;
-    const int64_t npx = (int64_t)B * H * W;
+    // frames of H rows at the given pitches (the mask takes the output pitch)
+    const int64_t ifr = (int64_t)H * in_pitch, ofr = (int64_t)H * out_pitch;
     // Inputs and outputs form a ring of sets that together exceed the
     // last-level cache (256 MB) several times, so a timed launch reads and
     // writes HBM as it would in use, not lines the previous launch left in
     // cache.
-    const int64_t in_bytes = npx * (int64_t)in_elem(kind);
-    const int64_t out_bytes = 3 * npx * (int64_t)out_elem(out_type);
-    const int64_t set_bytes = in_bytes + out_bytes + npx;
+    const int64_t in_bytes = B * ifr * (int64_t)in_elem(kind);
+    const int64_t out_bytes = 3 * B * ofr * (int64_t)out_elem(out_type);
+    const int64_t mask_bytes = B * ofr;
+    const int64_t set_bytes = in_bytes + out_bytes + mask_bytes;
     const int nset = (int)std::min<int64_t>(
         8, std::max<int64_t>(1, ((1ll << 30) + set_bytes - 1) / set_bytes));
     void *in = nullptr, *out = nullptr;
@@ -812,34 +854,37 @@ int sne_autotune(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int gr
     int rc = SNE_OK;
     if (hipMalloc(&in, nset * in_bytes) != hipSuccess ||
         hipMalloc(&out, nset * out_bytes) != hipSuccess ||
-        hipMalloc(&mask, nset * npx) != hipSuccess || hipStreamCreate(&st) != hipSuccess ||
+        hipMalloc(&mask, nset * mask_bytes) != hipSuccess || hipStreamCreate(&st) != hipSuccess ||
         hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         rc = SNE_ERR_HIP;
     }
     TileChoice best{0, 0, 0, 0};
+    int layout = 0;
     if (rc == SNE_OK) {
         const int threads = 256;
-        const int64_t nfill = nset * npx;
+        const int64_t nfill = nset * B * ifr;  // the padding columns too
         const int blocks = (int)((nfill + threads - 1) / threads);
         const int base = base_kind(kind);
         if (base == SNE_DEPTH_F32 || base == SNE_DISPARITY_F32)
             hipLaunchKernelGGL(fill_pattern<float>, dim3(blocks), dim3(threads), 0, st,
-                               (float *)in, nfill, W, base);
+                               (float *)in, nfill, (int)in_pitch, base);
         else
             hipLaunchKernelGGL(fill_pattern<uint16_t>, dim3(blocks), dim3(threads), 0, st,
-                               (uint16_t *)in, nfill, W, base);
+                               (uint16_t *)in, nfill, (int)in_pitch, base);
         sne_intrinsics K{(float)W, (float)W, (W - 1) * 0.5f, (H - 1) * 0.5f};
-        const int pxmax = max_px(in, out, mask, W, W, W, W, (int64_t)H * W, 3LL * H * W,
-                                 (int64_t)H * W, (int64_t)H * W, kind, out_type);
+        const int pxmax = max_px(in, out, mask, W, in_pitch, out_pitch, out_pitch, ifr, 3 * ofr,
+                                 ofr, ofr, kind, out_type);
+        layout = row_layout(in, in_pitch * (int64_t)in_elem(kind), ifr * in_elem(kind)) &&
+                 row_layout(out, out_pitch * (int64_t)out_elem(out_type),
+                            ofr * out_elem(out_type));
         int next = 0;
         auto launch = [&](const TileChoice &t) -> bool {
             const void *src = static_cast<const char *>(in) + next * in_bytes;
             void *dst = static_cast<char *>(out) + next * out_bytes;
-            uint8_t *msk = mask + next * npx;
+            uint8_t *msk = mask + next * mask_bytes;
             next = (next + 1) % nset;
-            return uniform_impl(ctx, src, B, H, W, W, (int64_t)H * W, &K, kind, grad, agg,
-                                out_type, dst, W, 3LL * H * W, msk, W, (int64_t)H * W, st,
-                                &t) == SNE_OK;
+            return uniform_impl(ctx, src, B, H, W, in_pitch, ifr, &K, kind, grad, agg, out_type,
+                                dst, out_pitch, 3 * ofr, msk, out_pitch, ofr, st, &t) == SNE_OK;
         };
         best = pick_fastest(tile_candidates(H, pxmax, true), default_tile(ctx, H, W, B, pxmax),
                             launch, st, e0, e1);
@@ -852,9 +897,14 @@ int sne_autotune(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int gr
     if (out) (void)hipFree(out);
     if (mask) (void)hipFree(mask);
     if (rc != SNE_OK) return rc;
-    ctx->cache[TileKey{H, W, batch_class(B), kind, grad, agg, out_type}] = best;
+    ctx->cache[TileKey{H, W, batch_class(B), kind, grad, agg, out_type, layout}] = best;
     report_tile(best, tile);
     return SNE_OK;
+}
+
+int sne_autotune(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int grad, int agg,
+                 int out_type, sne_tile *tile) {
+    return sne_autotune_pitched(ctx, H, W, B, W, W, kind, grad, agg, out_type, tile);
 }
 
 int sne_autotune_batched(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int grad,
@@ -896,13 +946,14 @@ int sne_autotune_save(const sne_ctx *ctx, const char *path) {
     if (!ctx || !path) return SNE_ERR_ARG;
     FILE *f = std::fopen(path, "w");
     if (!f) return SNE_ERR_IO;
-    std::fprintf(f, "# sne tile cache v1\n");
+    std::fprintf(f, "# sne tile cache v2: arch version H W batch-class kind grad agg out "
+                    "row-layout | cols-per-lane rows xcd-remap half-wave\n");
     for (const auto &kv : ctx->cache) {
         const TileKey &k = kv.first;
         const TileChoice &t = kv.second;
-        std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d %d %d\n", ctx->arch.c_str(),
-                     kTileCacheVersion, k.H, k.W, k.bclass, k.kind, k.grad, k.agg, k.out, t.px,
-                     t.rows, t.remap, t.half);
+        std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d %d %d %d\n", ctx->arch.c_str(),
+                     kTileCacheVersion, k.H, k.W, k.bclass, k.kind, k.grad, k.agg, k.out,
+                     k.layout, t.px, t.rows, t.remap, t.half);
     }
     const bool ok = std::fclose(f) == 0;
     return ok ? SNE_OK : SNE_ERR_IO;
@@ -916,16 +967,16 @@ int sne_autotune_load(sne_ctx *ctx, const char *path) {
     while (std::fgets(line, sizeof line, f)) {
         if (line[0] == '#') continue;
         char arch[128];
-        int ver, H, W, bc, kind, grad, agg, out, px, rows, remap, half = 0;
-        const int got = std::sscanf(line, "%127s %d %d %d %d %d %d %d %d %d %d %d %d", arch, &ver,
-                                    &H, &W, &bc, &kind, &grad, &agg, &out, &px, &rows, &remap,
-                                    &half);
-        if (got != 12 && got != 13) continue;
+        int ver, H, W, bc, kind, grad, agg, out, layout, px, rows, remap, half;
+        const int got =
+            std::sscanf(line, "%127s %d %d %d %d %d %d %d %d %d %d %d %d %d", arch, &ver, &H, &W,
+                        &bc, &kind, &grad, &agg, &out, &layout, &px, &rows, &remap, &half);
+        if (got != 14) continue;
         if (ctx->arch != arch || ver != kTileCacheVersion) continue;
         if (!valid_enum(kind, grad, agg, out) || !(px == 1 || px == 2 || px == 4) || rows < 1 ||
-            rows > 1024 || bc < 0 || bc > kUnevenClass)
+            rows > 1024 || bc < 0 || bc > kUnevenClass || (layout != 0 && layout != 1))
             continue;
-        ctx->cache[TileKey{H, W, bc, kind, grad, agg, out}] =
+        ctx->cache[TileKey{H, W, bc, kind, grad, agg, out, layout}] =
             TileChoice{px, rows, remap ? 1 : 0, half ? 1 : 0};
     }
     std::fclose(f);

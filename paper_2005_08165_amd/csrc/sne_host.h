@@ -16,10 +16,10 @@
 
 namespace sne {
 
-constexpr int kVersion = 10300;  // 1.3.0
+constexpr int kVersion = 10400;  // 1.4.0
 // Tile-shape cache entries carry the version of the kernels they were timed
 // on; it changes only when the kernels' speed characteristics do.
-constexpr int kTileCacheVersion = 10100;
+constexpr int kTileCacheVersion = 10200;
 constexpr int kSlots = 4;        // in-flight uneven batches per context
 constexpr int kEvalMaxPhis = 8;  // thresholds of sne_accuracy
 constexpr int kEvalRow = 2 + kEvalMaxPhis;  // per-block partials: sum psi, count, hits
@@ -33,11 +33,17 @@ constexpr int kUnevenClass = 3;
 constexpr int kOccEntries = 4 * 2 * 2 * 2 * 2 * 6;
 static_assert(kLenientFlag == SNE_LENIENT, "kernel-side flag mirrors the ABI");
 
+// Tile-cache key.  `layout` 1: every input and normal row starts at a
+// kRowAlign-byte boundary (frames stored with a padded pitch, or widths whose
+// rows happen to be such multiples); unaligned rows make the lines at strip
+// boundaries shared between wavefronts, which favours other tile shapes.
+constexpr int kRowAlign = 256;
 struct TileKey {
     int H, W, bclass, kind, grad, agg, out;
+    int layout = 0;
     bool operator<(const TileKey &o) const {
-        return std::tie(H, W, bclass, kind, grad, agg, out) <
-               std::tie(o.H, o.W, o.bclass, o.kind, o.grad, o.agg, o.out);
+        return std::tie(H, W, bclass, kind, grad, agg, out, layout) <
+               std::tie(o.H, o.W, o.bclass, o.kind, o.grad, o.agg, o.out, o.layout);
     }
 };
 struct TileChoice {
@@ -140,5 +146,8 @@ namespace sne {
 // Tile shape for a batch: forced shape, else the cache (for an uneven batch
 // first its own class), else the heuristic.
 TileChoice pick_tile(const sne_ctx *ctx, int H, int W, int64_t B, const Variant &v, int pxmax,
-                     bool uneven = false);
+                     bool uneven = false, int layout = 0);
+// 1 if rows of `row_bytes` and frames of `frame_bytes` from base `p` all start
+// at kRowAlign-byte boundaries.
+int row_layout(const void *p, int64_t row_bytes, int64_t frame_bytes);
 }  // namespace sne

@@ -26,7 +26,7 @@ SNE_OK = 0
 SNE_ERR_ARG, SNE_ERR_BUDGET, SNE_ERR_STATE = -1, -3, -5
 SNE_NOALLOC_MAX_FRAMES = 4096  # include/sne.h
 # version tag the library writes into (and requires of) tile-table entries
-TILE_CACHE_VERSION = 10100
+TILE_CACHE_VERSION = 10200
 STATUS = {0: "SNE_OK", -1: "SNE_ERR_ARG", -2: "SNE_ERR_UNSUPPORTED", -3: "SNE_ERR_BUDGET",
           -4: "SNE_ERR_HIP", -5: "SNE_ERR_STATE", -6: "SNE_ERR_FULL", -7: "SNE_ERR_IO"}
 
@@ -143,7 +143,12 @@ _SIGS = {
                                       _int, _vp], _int),
     "sne_set_tile": ([_vp, ctypes.POINTER(Tile)], _int),
     "sne_get_tile": ([_vp, _i32, _i32, _i32, _int, _int, _int, _int, ctypes.POINTER(Tile)], _int),
+    "sne_get_tile_pitched": ([_vp, _i32, _i32, _i32, _i64, _i64, _int, _int, _int, _int,
+                              ctypes.POINTER(Tile)], _int),
     "sne_autotune": ([_vp, _i32, _i32, _i32, _int, _int, _int, _int, ctypes.POINTER(Tile)], _int),
+    "sne_autotune_pitched": ([_vp, _i32, _i32, _i32, _i64, _i64, _int, _int, _int, _int,
+                              ctypes.POINTER(Tile)], _int),
+    "sne_row_pitch": ([_i32, _i32], _i64),
     "sne_autotune_batched": ([_vp, ctypes.POINTER(FrameDesc), _i32, _int, _int, _int, _int,
                               ctypes.POINTER(Tile)], _int),
     "sne_autotune_save": ([_vp, ctypes.c_char_p], _int),
@@ -257,6 +262,24 @@ def _dtype(kind_i: int):
     return KIND_DTYPE[kind_i & ~SNE_LENIENT]
 
 
+def row_pitch(W: int, dtype) -> int:
+    """sne_row_pitch: the smallest row pitch (elements) >= W whose rows start
+    at 256-byte boundaries, for a 1, 2 or 4-byte dtype."""
+    p = lib().sne_row_pitch(int(W), torch.empty((), dtype=dtype).element_size())
+    if p < 0:
+        check("sne_row_pitch", int(p))
+    return int(p)
+
+
+def pitched_empty(shape: Sequence[int], dtype=torch.float32, device="cuda") -> torch.Tensor:
+    """An uninitialised [..., H, W] tensor whose rows are padded to
+    row_pitch(W, dtype) elements (a view of the first W columns), the layout
+    that keeps every row on a 256-byte boundary."""
+    shape = tuple(int(x) for x in shape)
+    full = torch.empty(shape[:-1] + (row_pitch(shape[-1], dtype),), dtype=dtype, device=device)
+    return full[..., :shape[-1]]
+
+
 def _row_pitch(t: torch.Tensor) -> int:
     """Row pitch (elements) of a [..., H, W] tensor with unit column stride."""
     if t.stride(-1) != 1:
@@ -299,18 +322,27 @@ class Context:
         check("sne_set_tile", lib().sne_set_tile(self._h, ctypes.byref(t)))
 
     def get_tile(self, H, W, B=1, kind="depth_f32", grad="fd", agg="mean",
-                 out="f32") -> Tuple[int, int, int]:
+                 out="f32", in_pitch=None, out_pitch=None) -> Tuple[int, int, int]:
+        """sne_get_tile_pitched: the shape used for frames at these row
+        pitches (elements; dense, i.e. W, by default)."""
         t = Tile()
-        check("sne_get_tile", lib().sne_get_tile(self._h, H, W, B, _kind(kind),
-                                                 _enum(GRAD, grad, "grad"), _enum(AGG, agg, "agg"),
-                                                 _enum(OUT, out, "out"), ctypes.byref(t)))
+        check("sne_get_tile_pitched",
+              lib().sne_get_tile_pitched(self._h, H, W, B, in_pitch or W, out_pitch or W,
+                                         _kind(kind), _enum(GRAD, grad, "grad"),
+                                         _enum(AGG, agg, "agg"), _enum(OUT, out, "out"),
+                                         ctypes.byref(t)))
         return t.cols_per_lane, t.rows, t.lanes
 
-    def autotune(self, H, W, B=1, kind="depth_f32", grad="fd", agg="mean", out="f32"):
+    def autotune(self, H, W, B=1, kind="depth_f32", grad="fd", agg="mean", out="f32",
+                 in_pitch=None, out_pitch=None):
+        """sne_autotune_pitched on frames at these row pitches (dense by
+        default); returns (cols_per_lane, rows, lanes)."""
         t = Tile()
-        check("sne_autotune", lib().sne_autotune(self._h, H, W, B, _kind(kind),
-                                                 _enum(GRAD, grad, "grad"), _enum(AGG, agg, "agg"),
-                                                 _enum(OUT, out, "out"), ctypes.byref(t)))
+        check("sne_autotune_pitched",
+              lib().sne_autotune_pitched(self._h, H, W, B, in_pitch or W, out_pitch or W,
+                                         _kind(kind), _enum(GRAD, grad, "grad"),
+                                         _enum(AGG, agg, "agg"), _enum(OUT, out, "out"),
+                                         ctypes.byref(t)))
         return t.cols_per_lane, t.rows, t.lanes
 
     def autotune_batched(self, descs, kind="depth_u16", grad="fd", agg="mean", out="f16"):

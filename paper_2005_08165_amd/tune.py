@@ -30,6 +30,12 @@ WORKLOADS = [
 ]
 
 
+# uniform batches whose rows are padded to 256-byte multiples (sne_row_pitch);
+# they form a row-layout class of their own in the table
+PITCHED = [
+    (375, 1242, 128, "disparity_f32", "scharr", "median", "f32"),
+]
+
 # uneven persistent batches, tuned on the batch itself: (frames, input kind,
 # gradient filter, aggregation, output type)
 UNEVEN = [
@@ -43,8 +49,20 @@ def main(argv=None):
     from . import scenes
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=TABLE)
+    ap.add_argument("--pitched-only", action="store_true",
+                    help="keep the shipped entries and tune only the padded-pitch workloads")
     args = ap.parse_args(argv)
-    ctx = sne.Context(0, tuning=False)
+    ctx = sne.Context(0, tuning=args.pitched_only)
+    for H, W, B, kind, grad, agg, out in PITCHED:
+        pin = sne.row_pitch(W, sne._dtype(sne._kind(kind)))
+        pout = sne.row_pitch(W, sne.OUT_DTYPE[sne.OUT[out]])
+        t = ctx.autotune(H, W, B, kind, grad, agg, out, in_pitch=pin, out_pitch=pout)
+        print("%dx%d B=%d %s %s-%s %s, pitches %d/%d -> cols_per_lane %d rows %d lanes %d"
+              % (H, W, B, kind, grad, agg, out, pin, pout, *t), flush=True)
+    if args.pitched_only:
+        ctx.autotune_save(args.out)
+        print(args.out)
+        return 0
     for H, W, B, kind, grad, agg, out in WORKLOADS:
         t = ctx.autotune(H, W, B, kind, grad, agg, out)
         print("%dx%d B=%d %s %s-%s %s -> cols_per_lane %d rows %d lanes %d"

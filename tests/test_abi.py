@@ -36,7 +36,7 @@ def test_noalloc_rejects_bad_arguments_before_the_gpu():
 
 
 def test_version_and_status_strings():
-    assert sne.version() == 10300
+    assert sne.version() == 10400
     assert sne.status_string(0) == "ok"
     assert sne.status_string(-1) == "invalid argument"
     assert sne.status_string(12345) == "unknown status"
@@ -105,6 +105,28 @@ def test_null_context_errors():
     kx = (ctypes.c_float * 49)()
     assert L.sne_set_gradient_kernel(None, kx) == -1
     assert L.sne_set_gradient_kernel_n(None, 5, kx) == -1
+    assert L.sne_autotune_pitched(None, 10, 10, 1, 16, 16, 0, 0, 0, 0, None) == -1
+    assert L.sne_get_tile_pitched(None, 10, 10, 1, 16, 16, 0, 0, 0, 0, None) == -1
+    assert L.sne_get_tile_pitched(None, 10, 10, 1, 8, 16, 0, 0, 0, 0, ctypes.byref(t)) == -1
+
+
+def test_row_pitch():
+    """The smallest pitch >= W whose rows are 256-byte multiples."""
+    L = sne.lib()
+    assert L.sne_row_pitch(1242, 4) == 1280 and L.sne_row_pitch(640, 4) == 640
+    assert L.sne_row_pitch(1, 4) == 64 and L.sne_row_pitch(64, 4) == 64
+    assert L.sne_row_pitch(65, 4) == 128 and L.sne_row_pitch(320, 2) == 384
+    assert L.sne_row_pitch(1920, 2) == 1920 and L.sne_row_pitch(1242, 1) == 1280
+    assert L.sne_row_pitch(0, 4) < 0 and L.sne_row_pitch(10, 8) < 0 and L.sne_row_pitch(10, 3) < 0
+    import torch
+    assert sne.row_pitch(1242, torch.float32) == 1280
+    assert sne.row_pitch(1242, torch.uint8) == 1280 and sne.row_pitch(1242, torch.float16) == 1280
+    # without a context the heuristic applies to both layouts alike
+    t1, t2 = sne.Tile(), sne.Tile()
+    assert L.sne_get_tile_pitched(None, 375, 1242, 128, 1280, 1280, 3, 2, 1, 0,
+                                  ctypes.byref(t1)) == 0
+    assert L.sne_get_tile(None, 375, 1242, 128, 3, 2, 1, 0, ctypes.byref(t2)) == 0
+    assert (t1.cols_per_lane, t1.rows, t1.lanes) == (t2.cols_per_lane, t2.rows, t2.lanes)
 
 
 def test_default_tile_shape_without_context():
@@ -134,15 +156,21 @@ def test_shipped_tuning_table_is_well_formed():
         if line.startswith("#") or not line.strip():
             continue
         f = line.split()
-        assert len(f) == 13, line
-        arch, ver, H, W, bc, kind, grad, agg, out, px, rows, remap, half = (
+        assert len(f) == 14, line
+        arch, ver, H, W, bc, kind, grad, agg, out, layout, px, rows, remap, half = (
             [f[0]] + [int(x) for x in f[1:]])
         assert ver == sne.TILE_CACHE_VERSION and H >= 1 and W >= 1 and bc in (0, 1, 2, 3)
         assert kind in sne.KIND.values() and grad in sne.GRAD.values()
-        assert agg in sne.AGG.values() and out in (0, 1)
+        assert agg in sne.AGG.values() and out in (0, 1) and layout in (0, 1)
         assert px in (1, 2, 4) and 1 <= rows <= 1024 and remap in (0, 1) and half in (0, 1)
-        keys.add((H, W, bc, kind, grad, agg, out))
-    assert (480, 640, 2, 0, 1, 1, 0) in keys
+        # the row-layout class of a dense frame follows from its width; the
+        # uneven-batch class is always tuned and looked up as unaligned
+        if bc == 3:
+            assert layout == 0
+        keys.add((H, W, bc, kind, grad, agg, out, layout))
+    assert (480, 640, 2, 0, 1, 1, 0, 1) in keys          # headline, 2560-byte rows
+    assert (375, 1242, 2, 3, 2, 1, 0, 0) in keys         # stereo, dense
+    assert (375, 1242, 2, 3, 2, 1, 0, 1) in keys         # stereo, rows padded to 1280
     src = open(os.path.join(os.path.dirname(sne.LIB_PATH), "csrc", "sne_host.h")).read()
     assert "kTileCacheVersion = %d;" % sne.TILE_CACHE_VERSION in src
 
