@@ -586,16 +586,25 @@ def main():
                          "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
                          "algorithmic_bytes_per_launch": bytes_per_launch}}
         # wider filters (the LDS-tiled kernel): separable smoothing x derivative
-        wide = {5: ([1.0, 4.0, 6.0, 4.0, 1.0], [-1.0, -2.0, 0.0, 2.0, 1.0]),
-                7: ([1.0, 6.0, 15.0, 20.0, 15.0, 6.0, 1.0], [-1.0, -4.0, -5.0, 0.0, 5.0, 4.0, 1.0])}
-        for n, (smooth, deriv) in wide.items():
-            log("custom %dx%d gradient kernel on the same batches" % (n, n))
-            cctx.set_gradient_kernel([[a * b for b in deriv] for a in smooth])
+        # products, and one 5x5 that is not a product (the general taps)
+        s5, d5 = [1.0, 4.0, 6.0, 4.0, 1.0], [-1.0, -2.0, 0.0, 2.0, 1.0]
+        s7 = [1.0, 6.0, 15.0, 20.0, 15.0, 6.0, 1.0]
+        d7 = [-1.0, -4.0, -5.0, 0.0, 5.0, 4.0, 1.0]
+        g5 = [[a * b for b in d5] for a in s5]
+        g5[0][0] += 1.0
+        wide = {"5": (5, [[a * b for b in d5] for a in s5], "%s (column) x %s (row)" % (s5, d5)),
+                "7": (7, [[a * b for b in d7] for a in s7], "%s (column) x %s (row)" % (s7, d7)),
+                "5_general": (5, g5, "%s (column) x %s (row), plus 1 at the top left: not a "
+                                     "product" % (s5, d5))}
+        for tag, (n, kx, what) in wide.items():
+            log("custom %dx%d gradient kernel (%s) on the same batches" % (n, n, tag))
+            cctx.set_gradient_kernel(kx)
             wall_w, ev_w = time_launches(torch, step_cus, max(args.warmup // 3, 5), csteps)
             gbs = bytes_per_launch / (ev_w / csteps) / 1e9
-            res["custom%d_kernel_batch" % n] = {
-                "workload": "batch64_480x640_f32depth_custom%dx%d_%s" % (n, n, args.agg),
-                "kernel": "K_x = %s (column) x %s (row)" % (smooth, deriv),
+            res["custom%s_kernel_batch" % tag] = {
+                "workload": "batch64_480x640_f32depth_custom%dx%d%s_%s" % (
+                    n, n, "_general" if "general" in tag else "", args.agg),
+                "kernel": "K_x = " + what,
                 "us_per_launch": round(ev_w / csteps * 1e6, 2),
                 "mpix_per_s": round(px * csteps / ev_w / 1e6, 1),
                 "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,

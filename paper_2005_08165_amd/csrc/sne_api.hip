@@ -59,6 +59,31 @@ void custom_weights(const float kx[9], GradW &w) {
     }
 }
 
+// K = kc kr^T for an n x n kernel, if it is one: kc is the column through the
+// largest weight and kr that weight's row divided by it; accepted when every
+// product reproduces its weight to 2^-21 of the largest (exact for integer
+// smoothing x derivative products).  Sets w.separable.
+void separable_factors(const float *k, int n, WideArgs &w) {
+    w.separable = 0;
+    int p = 0, q = 0;
+    for (int i = 0; i < n * n; ++i)
+        if (std::fabs(k[i]) > std::fabs(k[p * n + q])) {
+            p = i / n;
+            q = i % n;
+        }
+    const double piv = k[p * n + q];
+    if (piv == 0.0) return;
+    for (int i = 0; i < n; ++i) {
+        w.kc[i] = k[i * n + q];
+        w.kr[i] = (float)(k[p * n + i] / piv);
+    }
+    const double tol = std::fabs(piv) * std::ldexp(1.0, -21);
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b)
+            if (std::fabs((double)w.kc[a] * (double)w.kr[b] - (double)k[a * n + b]) > tol) return;
+    w.separable = 1;
+}
+
 void grad_weights(int grad, GradW &w) {
     double a = 0.0;
     switch (grad) {
@@ -326,6 +351,7 @@ int uniform_impl(sne_ctx *ctx, const void *in, int32_t B, int32_t H, int32_t W, 
             sum += (double)w.kx[i];
         }
         w.ksum = (float)sum;
+        separable_factors(ctx->custom_kx, ctx->custom_n, w);
         if (hipSetDevice(ctx->device) != hipSuccess) return SNE_ERR_HIP;
         return launch_wide(v, w, (hipStream_t)stream) == hipSuccess ? SNE_OK : SNE_ERR_HIP;
     }

@@ -71,6 +71,8 @@ struct WideArgs {
     int32_t R;                                      // 2 or 3
     float kx[kWideMaxN * kWideMaxN];                // K_x row-major, (2R+1)^2 used
     float ksum;                                     // sum of all weights
+    int32_t separable;                              // 1: K_x[a][b] = kc[a] kr[b]
+    float kc[kWideMaxN], kr[kWideMaxN];
 };
 
 // Uneven batch.  Its tables are one block of device memory that the host

@@ -898,7 +898,10 @@ __global__ __launch_bounds__(kBlock) SNE_OCCUPANCY void sne_uniform_kernel(Unifo
 //   G = sum_ab K_ab (d_ab - d_r) + (sum K) d_r            (disparity)
 // The neighbourhood of n_z stays the 8-connected one, and a pixel is kept iff
 // its whole (2R+1)x(2R+1) window is inside the frame and valid.
-template <int KIND, int R, int AGG, int OUT>
+// SEP: K_x = kc kr^T (a smoothing column times a derivative row, say); then
+// each window row's two weighted sums serve every pixel of the column, so a
+// pixel takes 2(2R+1) FMAs of row sums instead of 2(2R+1)^2 taps.
+template <int KIND, int R, int AGG, int OUT, bool SEP>
 __global__ __launch_bounds__(kBlock) void sne_wide_kernel(WideArgs a) {
     constexpr int N = 2 * R + 1, LW = kWideTW + 2 * R, LH = kWideTH + 2 * R;
     constexpr int RPT = kWideTH / kWavesPerBlock;  // rows per thread
@@ -967,15 +970,28 @@ __global__ __launch_bounds__(kBlock) void sne_wide_kernel(WideArgs a) {
 #pragma unroll
         for (int b = 3; b < N; b += 2)
             rmin = b + 1 < N ? vmin3(rmin, zv[b], zv[b + 1]) : vmin(rmin, zv[b]);
+        float hr = 0.f, hc = 0.f;  // SEP: sum_b kr[b] d[b], sum_b kc[b] d[b]
+        if constexpr (SEP) {
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+                hr = fmaf(a.kr[b], d[b], hr);
+                hc = fmaf(a.kc[b], d[b], hc);
+            }
+        }
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
             const int ka = ar - i;
             if (ka < 0 || ka > 2 * R) continue;
             mn[i] = vmin(mn[i], rmin);
+            if constexpr (SEP) {
+                gu[i] = fmaf(a.kc[ka], hr, gu[i]);  // K_x row ka = kc[ka] kr
+                gv[i] = fmaf(a.kr[ka], hc, gv[i]);  // K_y row ka = K_x column ka = kr[ka] kc
+            } else {
 #pragma unroll
-            for (int b = 0; b < N; ++b) {
-                gu[i] = fmaf(a.kx[ka * N + b], d[b], gu[i]);
-                gv[i] = fmaf(a.kx[b * N + ka], d[b], gv[i]);
+                for (int b = 0; b < N; ++b) {
+                    gu[i] = fmaf(a.kx[ka * N + b], d[b], gu[i]);
+                    gv[i] = fmaf(a.kx[b * N + ka], d[b], gv[i]);
+                }
             }
         }
     }
@@ -1203,28 +1219,30 @@ hipError_t uniform_variant(const Variant &v, const UniformArgs &a, int grid, hip
     }
     return SNE_DISPATCH(uniform_px, KIND, v, a, grid, s);
 }
-template <int KIND, int R>
+template <int KIND, int R, bool SEP>
 hipError_t wide_r(const Variant &v, const WideArgs &a, hipStream_t s) {
     const dim3 grid((unsigned)a.nblocks), block(kBlock);
     if (v.agg == AGG_MEAN) {
         if (v.out == OUT_F32)
-            hipLaunchKernelGGL((sne_wide_kernel<KIND, R, AGG_MEAN, OUT_F32>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((sne_wide_kernel<KIND, R, AGG_MEAN, OUT_F32, SEP>), grid, block, 0,
+                               s, a);
         else
-            hipLaunchKernelGGL((sne_wide_kernel<KIND, R, AGG_MEAN, OUT_F16>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((sne_wide_kernel<KIND, R, AGG_MEAN, OUT_F16, SEP>), grid, block, 0,
+                               s, a);
     } else {
         if (v.out == OUT_F32)
-            hipLaunchKernelGGL((sne_wide_kernel<KIND, R, AGG_MEDIAN, OUT_F32>), grid, block, 0, s,
-                               a);
+            hipLaunchKernelGGL((sne_wide_kernel<KIND, R, AGG_MEDIAN, OUT_F32, SEP>), grid, block,
+                               0, s, a);
         else
-            hipLaunchKernelGGL((sne_wide_kernel<KIND, R, AGG_MEDIAN, OUT_F16>), grid, block, 0, s,
-                               a);
+            hipLaunchKernelGGL((sne_wide_kernel<KIND, R, AGG_MEDIAN, OUT_F16, SEP>), grid, block,
+                               0, s, a);
     }
     return hipGetLastError();
 }
 template <int KIND>
 hipError_t wide_variant(const Variant &v, const WideArgs &a, hipStream_t s) {
-    if (a.R == 2) return wide_r<KIND, 2>(v, a, s);
-    if (a.R == 3) return wide_r<KIND, 3>(v, a, s);
+    if (a.R == 2) return a.separable ? wide_r<KIND, 2, true>(v, a, s) : wide_r<KIND, 2, false>(v, a, s);
+    if (a.R == 3) return a.separable ? wide_r<KIND, 3, true>(v, a, s) : wide_r<KIND, 3, false>(v, a, s);
     return hipErrorInvalidValue;
 }
 template <int KIND>
