@@ -59,3 +59,27 @@ def test_row_layout_class_of_the_tile_cache():
     # 480x640 rows are 2560 bytes: dense frames are already in the aligned class
     a = (480, 640, 64, "depth_f32", "sobel", "median", "f32")
     assert ctx.get_tile(*a) == ctx.get_tile(*a, in_pitch=768, out_pitch=768)
+
+
+def test_pitched_autotune_records_the_padded_class():
+    """sne_autotune_pitched on padded frames keeps its shape for the padded
+    row layout only: the dense lookup of the same variant is unchanged."""
+    ctx = sne.Context(0, tuning=False)
+    args = (96, 1242, 8, "depth_f32", "fd", "mean", "f32")
+    dense_before = ctx.get_tile(*args)
+    t = ctx.autotune(*args, in_pitch=1280, out_pitch=1280)
+    assert t[0] in (1, 2) and 1 <= t[1] <= 1024 and t[2] in (32, 64)
+    assert ctx.get_tile(*args, in_pitch=1280, out_pitch=1280) == t
+    assert ctx.get_tile(*args) == dense_before
+    # and the tuned shape gives the dense results, bit for bit
+    cam = S.camera_for(96, 1242)
+    dense = torch.stack([S.make_cluttered(3100 + i, cam, device="cuda").raw for i in range(8)])
+    raw = sne.pitched_empty(tuple(dense.shape), torch.float32)
+    raw.copy_(dense)
+    nd, md = sne.estimate_uniform(dense, cam.as_tuple(), "depth_f32", "fd", "mean", ctx=ctx)
+    nrm = sne.pitched_empty((8, 3, 96, 1242), torch.float32)
+    msk = sne.pitched_empty((8, 96, 1242), torch.uint8)
+    sne.estimate_uniform(raw, cam.as_tuple(), "depth_f32", "fd", "mean", normals=nrm, mask=msk,
+                         ctx=ctx)
+    torch.cuda.synchronize()
+    assert torch.equal(nd, nrm) and torch.equal(md, msk)
