@@ -56,6 +56,9 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// What a missing mask reads as: every pixel of the group evaluated.
+__device__ const uint32_t kAllValid = 0xffffffffu;
+
 template <int OUT, int V> struct EstVec;
 template <> struct EstVec<OUT_F32, 1> { using T = float; };
 template <> struct EstVec<OUT_F32, 4> { typedef float T __attribute__((ext_vector_type(4))); };
@@ -76,8 +79,8 @@ __global__ __launch_bounds__(kEvalBlock) void eval_partial(EvalArgs a) {
     using GT = typename EstVec<OUT_F32, V>::T;
     using MT = typename std::conditional<V == 4, uint32_t, uint8_t>::type;
     double sum = 0.0;
-    double cnt = 0.0;
-    double hit[kEvalMaxPhis] = {};
+    uint32_t cnt = 0;  // per thread: far below 2^32
+    uint32_t hit[kEvalMaxPhis] = {};
     const int64_t hwv = a.hw / V, nv = a.npx / V;  // in groups of V pixels
     const int64_t stride = (int64_t)gridDim.x * kEvalBlock;
     int64_t i = (int64_t)blockIdx.x * kEvalBlock + threadIdx.x;
@@ -92,22 +95,26 @@ __global__ __launch_bounds__(kEvalBlock) void eval_partial(EvalArgs a) {
     const GT *gt = reinterpret_cast<const GT *>(a.gt);
     const MT *mask = reinterpret_cast<const MT *>(a.mask);
     for (; i < nv; i += stride) {
-        const MT mw = mask ? mask[i] : (MT)~(MT)0;
-        if (mw) {
-            const int64_t base = b * 3 * hwv + q;
-            const ET ex = est[base], ey = est[base + hwv], ez = est[base + 2 * hwv];
-            const GT gx = gt[base], gy = gt[base + hwv], gz = gt[base + 2 * hwv];
+        // every load of the group at once (the planes are read whatever the
+        // mask says)
+        const MT *mp = mask ? mask + i : reinterpret_cast<const MT *>(&kAllValid);
+        const MT mw = *mp;
+        const int64_t base = b * 3 * hwv + q;
+        const ET ex = est[base], ey = est[base + hwv], ez = est[base + 2 * hwv];
+        const GT gx = gt[base], gy = gt[base + hwv], gz = gt[base + 2 * hwv];
+        // no branch on the mask: every pixel's angle is formed and the mask
+        // selects what is counted (a branch would let the compiler sink the
+        // plane loads behind the mask's round trip)
 #pragma unroll
-            for (int k = 0; k < V; ++k) {
-                if (!((mw >> (8 * k)) & 0xff)) continue;
-                const float psi = angle_deg(lane_of(ex, k), lane_of(ey, k), lane_of(ez, k),
-                                            lane_of(gx, k), lane_of(gy, k), lane_of(gz, k));
-                sum += psi;
-                cnt += 1.0;
+        for (int k = 0; k < V; ++k) {
+            const bool ok = ((mw >> (8 * k)) & 0xff) != 0;
+            const float psi = angle_deg(lane_of(ex, k), lane_of(ey, k), lane_of(ez, k),
+                                        lane_of(gx, k), lane_of(gy, k), lane_of(gz, k));
+            sum += ok ? (double)psi : 0.0;
+            cnt += ok ? 1u : 0u;
 #pragma unroll
-                for (int j = 0; j < kEvalMaxPhis; ++j)
-                    if (j < a.nphi && psi <= a.phis[j]) hit[j] += 1.0;
-            }
+            for (int j = 0; j < kEvalMaxPhis; ++j)
+                hit[j] += (ok && j < a.nphi && psi <= a.phis[j]) ? 1u : 0u;
         }
         b += sb;
         q += sq;
@@ -119,14 +126,15 @@ __global__ __launch_bounds__(kEvalBlock) void eval_partial(EvalArgs a) {
     __shared__ double red[kEvalWaves][kEvalRow];
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     sum = wave_sum(sum);
-    cnt = wave_sum(cnt);
+    const double cntd = wave_sum((double)cnt);
+    double hitd[kEvalMaxPhis];
 #pragma unroll
-    for (int j = 0; j < kEvalMaxPhis; ++j) hit[j] = wave_sum(hit[j]);
+    for (int j = 0; j < kEvalMaxPhis; ++j) hitd[j] = wave_sum((double)hit[j]);
     if (lane == 0) {
         red[wave][0] = sum;
-        red[wave][1] = cnt;
+        red[wave][1] = cntd;
 #pragma unroll
-        for (int j = 0; j < kEvalMaxPhis; ++j) red[wave][2 + j] = hit[j];
+        for (int j = 0; j < kEvalMaxPhis; ++j) red[wave][2 + j] = hitd[j];
     }
     __syncthreads();
     if (threadIdx.x < kEvalRow) {
