@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2005_08165_amd", "csrc", "sne_kernels.hip")
+TUNING_FILE = os.path.join(ROOT, "paper_2005_08165_amd", "tuning.txt")
 
 
 def log(*a):
@@ -43,14 +44,21 @@ def kernel_hash() -> str:
     return hashlib.sha256(src.encode()).hexdigest()[:16]
 
 
+def table_hash() -> str:
+    """Hash of the shipped tuning table (it also fixes each entry's block
+    order, which changes the traffic but not the tile shape)."""
+    return hashlib.sha256(open(TUNING_FILE, "rb").read()).hexdigest()[:16]
+
+
 def measured_traffic(workload: str, tile):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source with the same tile shape."""
+    it was taken on the current kernel source and tuning table with the same
+    tile shape."""
     try:
         d = json.load(open(TRAFFIC_FILE))
         e = d.get(workload)
-        if (e and e.get("kernel_sha") == kernel_hash() and tile is not None
-                and e.get("tile") == ",".join(str(x) for x in tile)):
+        if (e and e.get("kernel_sha") == kernel_hash() and e.get("table_sha") == table_hash()
+                and tile is not None and e.get("tile") == ",".join(str(x) for x in tile)):
             return e.get("bytes_per_launch")
     except (OSError, ValueError):
         pass

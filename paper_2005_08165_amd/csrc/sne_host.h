@@ -16,10 +16,12 @@
 
 namespace sne {
 
-constexpr int kVersion = 10400;  // 1.4.0
+constexpr int kVersion = 10500;  // 1.5.0
 // Tile-shape cache entries carry the version of the kernels they were timed
 // on; it changes only when the kernels' speed characteristics do.
 constexpr int kTileCacheVersion = 10200;
+constexpr int kChunkOrder = 16;     // the runs-of-G block order the tuner tries
+constexpr int kMaxChunkOrder = 1024;  // largest G a tuning table may name
 constexpr int kSlots = 4;        // in-flight uneven batches per context
 constexpr int kEvalMaxPhis = 8;  // thresholds of sne_accuracy
 constexpr int kEvalRow = 2 + kEvalMaxPhis;  // per-block partials: sum psi, count, hits
@@ -47,7 +49,8 @@ struct TileKey {
     }
 };
 struct TileChoice {
-    int px, rows, remap;
+    int px, rows;
+    int remap;     // block order (UniformArgs::xcd_remap); 0 for the persistent kernel
     int half = 0;  // 1: half-wave mode (two 32-lane tiles per wavefront)
 };
 

@@ -55,7 +55,8 @@ struct UniformArgs {
     int32_t B;
     int32_t nstrips, nbands, rows;  // tile grid of one frame
     int32_t ntiles;                 // B * nbands * nstrips
-    int32_t xcd_remap;              // 1: give each XCD a contiguous tile range
+    int32_t xcd_remap;              // block order: 0 plain, 1 one contiguous tile
+                                    // range per XCD, G > 1 runs of G blocks per XCD
     GradW gw;
 };
 

@@ -858,9 +858,23 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     return x * q + min(x, rem) + i;
 }
 
+// Runs of G: XCD x takes runs of G consecutive blocks, the runs of the 8
+// XCDs interleaved, so the blocks resident at any time still cover one
+// window of the batch (the plain order's DRAM locality) while vertically
+// adjacent tiles mostly meet in one XCD's L2 (their shared halo rows are
+// fetched once).  Blocks of a partial last round of 8 G keep their order.
+__device__ __forceinline__ int xcd_chunk(int b, int nb, int G) {
+    const int full = nb / (8 * G) * (8 * G);
+    if (b >= full) return b;
+    const int x = b & 7, i = b >> 3;
+    return (i / G) * (8 * G) + x * G + (i % G);
+}
+
 template <int KIND, int GK, int AGG, int OUT, int PX, bool HALF, bool LEN>
 __global__ __launch_bounds__(kBlock) SNE_OCCUPANCY void sne_uniform_kernel(UniformArgs a) {
-    const int b = a.xcd_remap ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int b = a.xcd_remap == 1   ? xcd_block(blockIdx.x, gridDim.x)
+                  : a.xcd_remap > 1 ? xcd_chunk(blockIdx.x, gridDim.x, a.xcd_remap)
+                                    : (int)blockIdx.x;
     // wave-uniform by construction; readfirstlane lets the compiler keep the
     // frame's buffer resource in scalar registers
     const int tile = __builtin_amdgcn_readfirstlane(b * kWavesPerBlock + (int)(threadIdx.x >> 6));

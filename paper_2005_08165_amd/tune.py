@@ -51,8 +51,11 @@ def main(argv=None):
     ap.add_argument("--out", default=TABLE)
     ap.add_argument("--pitched-only", action="store_true",
                     help="keep the shipped entries and tune only the padded-pitch workloads")
+    ap.add_argument("--uniform-only", action="store_true",
+                    help="keep the shipped entries and tune only the uniform workloads "
+                         "(dense and padded)")
     args = ap.parse_args(argv)
-    ctx = sne.Context(0, tuning=args.pitched_only)
+    ctx = sne.Context(0, tuning=args.pitched_only or args.uniform_only)
     for H, W, B, kind, grad, agg, out in PITCHED:
         pin = sne.row_pitch(W, sne._dtype(sne._kind(kind)))
         pout = sne.row_pitch(W, sne.OUT_DTYPE[sne.OUT[out]])
@@ -67,6 +70,10 @@ def main(argv=None):
         t = ctx.autotune(H, W, B, kind, grad, agg, out)
         print("%dx%d B=%d %s %s-%s %s -> cols_per_lane %d rows %d lanes %d"
               % (H, W, B, kind, grad, agg, out, *t), flush=True)
+    if args.uniform_only:
+        ctx.autotune_save(args.out)
+        print(args.out)
+        return 0
     for n, kind, grad, agg, out in UNEVEN:
         shapes, Ks, ki, frames = scenes.uneven_batch(n, device="cuda")
         ctx.set_intrinsics_table(Ks)

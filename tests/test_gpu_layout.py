@@ -53,7 +53,13 @@ def test_row_layout_class_of_the_tile_cache():
     args = (375, 1242, 128, "disparity_f32", "scharr", "median", "f32")
     dense = ctx.get_tile(*args)
     padded = ctx.get_tile(*args, in_pitch=1280, out_pitch=1280)
-    assert dense == (2, 2, 64) and padded != dense
+    # the shipped table's two stereo entries (row-layout field 0 and 1)
+    shipped = {}
+    for line in open(sne.TUNING_TABLE):
+        f = line.split()
+        if not line.startswith("#") and f[2:9] == ["375", "1242", "2", "3", "2", "1", "0"]:
+            shipped[int(f[9])] = (int(f[10]), int(f[11]), 32 if f[13] == "1" else 64)
+    assert dense == shipped[0] and padded == shipped[1] and padded != dense
     # 64-byte but not 256-byte rows: the dense class
     assert ctx.get_tile(*args, in_pitch=1248, out_pitch=1248) == dense
     # 480x640 rows are 2560 bytes: dense frames are already in the aligned class

@@ -6,6 +6,7 @@ mean <= 0.02 deg and max <= 0.1 deg (rounding a unit vector to binary16 alone
 moves it by up to ~0.03 deg).  The mask must match bit for bit, masked-out
 pixels must be +0.0 in every channel.  Inputs are seeded synthetic scenes.
 """
+import os
 import sys
 
 import numpy as np
@@ -446,6 +447,51 @@ def test_disparity_rows_need_equal_focal_lengths():
         srv.release(t)
     finally:
         srv.close()
+
+
+def _table_arch():
+    """The architecture string this GPU's tuning-table lines carry."""
+    import tempfile
+    ctx = sne.Context(0)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "t.txt")
+        ctx.autotune_save(path)
+        lines = [l for l in open(path) if l.strip() and not l.startswith("#")]
+    assert lines, "the shipped table has no entry for this GPU"
+    return lines[0].split()[0]
+
+
+def test_block_orders_bitwise(tmp_path):
+    """The block orders (plain, one tile range per XCD, runs of G blocks per
+    XCD, including a G that leaves a partial last round) only renumber the
+    tiles: every pixel is written once and the results are the same bits."""
+    B, H, W = 16, 480, 640
+    cam = S.Camera(H, W, *S.INDOOR_K)
+    raw = torch.stack([S.make_cluttered(1000 + i, cam, device="cuda").raw for i in range(B)])
+    arch = _table_arch()
+    ref = None
+    # 1200 blocks: runs of 16 leave a partial last round of 48 blocks, runs
+    # of 7 one of 24
+    for order in (0, 1, 16, 7):
+        path = str(tmp_path / ("order%d.txt" % order))
+        with open(path, "w") as f:
+            f.write("%s %d %d %d %d %d %d %d %d %d %d %d %d %d\n" % (
+                arch, sne.TILE_CACHE_VERSION, H, W, 2, sne.KIND["depth_f32"], sne.GRAD["sobel"],
+                sne.AGG["median"], 0, 1, 4, 4, order, 1))
+        ctx = sne.Context(0, tuning=False)
+        ctx.autotune_load(path)
+        assert ctx.get_tile(H, W, B, "depth_f32", "sobel", "median", "f32") == (4, 4, 32)
+        n = torch.full((B, 3, H, W), float("nan"), device="cuda")
+        m = torch.full((B, H, W), 7, dtype=torch.uint8, device="cuda")
+        sne.estimate_uniform(raw, cam.as_tuple(), "depth_f32", "sobel", "median", normals=n,
+                             mask=m, ctx=ctx)
+        torch.cuda.synchronize()
+        assert not torch.isnan(n).any() and not (m == 7).any(), order
+        if ref is None:
+            ref = (n, m)
+        else:
+            assert torch.equal(n.view(torch.int32), ref[0].view(torch.int32)), order
+            assert torch.equal(m, ref[1]), order
 
 
 def test_autotune_and_tuning_table():
