@@ -285,8 +285,23 @@ def accuracy_eval(torch, S, sne, reps=100, phis=(11.25, 22.5, 30.0)):
 
     wall, ev = time_launches(torch, call, 10, reps)
     px = B * H * W
+    # the same scenes without depth noise or holes (not timed): the noise of
+    # the benchmark recipe, not the estimator, dominates the errors above
+    del copies
+    clean = [S.make_cluttered(1000 + i, cam, device="cuda", noise=0.0, holes=0.0, need_gt=True)
+             for i in range(8)]
+    craw = torch.stack([f.raw for f in clean])
+    cgt = torch.stack([f.gt.float() for f in clean]).contiguous()
+    cn, cm = sne.estimate_uniform(craw, cam.as_tuple(), "depth_f32", "sobel", "median", ctx=ctx)
+    cA, cP, cnt = ctx.accuracy(cn, cgt, cm, phis)
     return {"frames": B, "grad": "sobel", "agg": "median", "e_A_deg": round(eA, 4),
             "e_P": {str(p): round(v, 4) for p, v in zip(phis, eP)}, "pixels_evaluated": m,
+            "note": "the benchmark's scenes carry 0.5 % multiplicative depth noise, which "
+                    "dominates per-pixel normals at 480x640; clean_frames: the first 8 scenes "
+                    "without noise or holes",
+            "clean_frames": {"frames": 8, "e_A_deg": round(cA, 4),
+                             "e_P": {str(p): round(v, 4) for p, v in zip(phis, cP)},
+                             "pixels_evaluated": cnt},
             "us_per_call": round(ev / reps * 1e6, 2),
             "gpx_per_s": round(px * reps / ev / 1e9, 1),
             "achieved_GBs": round(px * 25 * reps / ev / 1e9, 1),
