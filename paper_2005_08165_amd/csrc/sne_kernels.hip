@@ -915,6 +915,10 @@ __global__ __launch_bounds__(kBlock) SNE_OCCUPANCY void sne_uniform_kernel(Unifo
 // SEP: K_x = kc kr^T (a smoothing column times a derivative row, say); then
 // each window row's two weighted sums serve every pixel of the column, so a
 // pixel takes 2(2R+1) FMAs of row sums instead of 2(2R+1)^2 taps.
+// Blocks run in runs of kWideRun per XCD (xcd_chunk), so the tiles above and
+// below a tile mostly share its apron rows through one L2.
+constexpr int kWideRun = 16;
+
 template <int KIND, int R, int AGG, int OUT, bool SEP>
 __global__ __launch_bounds__(kBlock) void sne_wide_kernel(WideArgs a) {
     constexpr int N = 2 * R + 1, LW = kWideTW + 2 * R, LH = kWideTH + 2 * R;
@@ -924,7 +928,7 @@ __global__ __launch_bounds__(kBlock) void sne_wide_kernel(WideArgs a) {
     __shared__ float2 T[LH * LW];  // (z, s)
     using IT = typename Raw<KIND>::T;
     using OT = typename Out<OUT>::T;
-    const int blk = (int)blockIdx.x;
+    const int blk = xcd_chunk((int)blockIdx.x, (int)gridDim.x, kWideRun);
     if (blk >= a.nblocks) return;
     const int per_frame = a.ntx * a.nty;
     const int frame = blk / per_frame;
