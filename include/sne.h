@@ -279,7 +279,11 @@ int sne_get_tile_pitched(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int64_t 
  * up to 8 sets of input and outputs, at least 1 GB together, are used in
  * turn so that launches read and write HBM rather than the last-level cache),
  * keep the fastest in ctx's cache for the frame-size class of H x W, and
- * report it (tile may be NULL).  Synchronous; seconds at most. */
+ * report it (tile may be NULL).  Each shape is timed in three orders of the
+ * thread blocks over the GPU's 8 XCDs (launch order, one contiguous tile
+ * range per XCD, runs of 16 consecutive blocks per XCD); the order is part of
+ * the cached choice (sne_tile does not report it; the saved table does).
+ * Synchronous; seconds at most. */
 int sne_autotune(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int kind, int grad, int agg,
                  int out_type, sne_tile *tile);
 
@@ -301,8 +305,13 @@ int sne_autotune_pitched(sne_ctx *ctx, int32_t H, int32_t W, int32_t B, int64_t 
 int sne_autotune_batched(sne_ctx *ctx, const sne_frame *frames, int32_t n, int kind, int grad,
                          int agg, int out_type, sne_tile *tile);
 
-/* Save / load the tile-shape cache as text.  Entries recorded for another
- * GPU architecture or library version are ignored on load. */
+/* Save / load the tile-shape cache as text, one entry per line: architecture,
+ * cache version, H, W, batch class, kind, grad, agg, out_type, row layout
+ * (1: rows on 256-byte boundaries) | columns per lane, rows, block order (0
+ * launch order, 1 one tile range per XCD, G >= 2 runs of G blocks per XCD,
+ * at most 1024), half wave (0/1).  Entries recorded for another GPU
+ * architecture or library version, or with values outside those ranges, are
+ * ignored on load. */
 int sne_autotune_save(const sne_ctx *ctx, const char *path);
 int sne_autotune_load(sne_ctx *ctx, const char *path);
 
